@@ -1,0 +1,267 @@
+"""FP64 CPU oracle of the CFS chaos game -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's ``cpu_baseline`` leg may
+import this package.  The GPU library never imports, links or calls it, and it
+imports nothing from the GPU library.
+
+The arithmetic lives in ``cfs_oracle.c`` (plain C, FP64, single thread, no FMA
+contraction); this module only builds it with gcc and marshals numpy arrays.
+Every function cites the part of the paper it follows in the C source.
+
+Parity status:
+  philox4x32_10      pinned: known-answer vectors, rocRAND host generator
+  thresholds/select  pinned: exhaustive over all 2^32 draws, closed form
+  chaos_count        pinned: invariant-measure moments, uniform square,
+                     Sierpinski box dimension, address containment,
+                     composition order
+  chaos_depth        pinned: Menger occupancy of the 3^k grid and box
+                     dimension for the 3D points; the projected depth image
+                     itself is parity unpinned beyond the oracle
+  splat_gauss        pinned: total mass closed form, separable kernel sums
+  splat_gauss_backward pinned: central finite differences of splat_gauss,
+                     zero gradient at the target
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cfs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_cfs_oracle.so")
+
+FINAL_KINDS = {"identity": 0, "swirl": 1, "twist_camera": 2, "stretch": 3}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain IEEE FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _System(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_maps", C.c_int32),
+                ("A", C.POINTER(C.c_float)), ("b", C.POINTER(C.c_float)),
+                ("prob", C.POINTER(C.c_double)), ("final_kind", C.c_int32),
+                ("final_params", C.POINTER(C.c_float))]
+
+
+class _Run(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32),
+                ("n_points", C.c_uint32), ("point_offset", C.c_uint32),
+                ("n_iters", C.c_uint32), ("burn_in", C.c_uint32)]
+
+
+class _Window(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32),
+                ("channels", C.c_int32), ("lo", C.c_float * 2),
+                ("hi", C.c_float * 2)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        lib.orc_philox4x32_10.argtypes = [P, P, P]
+        lib.orc_philox_many.argtypes = [C.c_uint64, P, P, C.c_int64]
+        lib.orc_thresholds.argtypes = [P, C.c_int, P]
+        lib.orc_select.argtypes = [C.c_uint32, P, C.c_int]
+        lib.orc_select_histogram.argtypes = [P, C.c_int, P]
+        lib.orc_chaos_count.argtypes = [P, P, P, P, P, P, P, P, P]
+        lib.orc_chaos_depth.argtypes = [P, P, P, C.c_float, P, P, P, P, P, P]
+        lib.orc_splat_gauss.argtypes = [P, P, P, C.c_double, P, P]
+        lib.orc_splat_gauss_backward.argtypes = [P, P, P, C.c_double, P, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class _Keep:
+    """Holds the numpy buffers a ctypes struct points into."""
+
+    def __init__(self, system):
+        d = int(system["dim"])
+        self.A = np.ascontiguousarray(system["A"], dtype=np.float32).reshape(-1)
+        self.b = np.ascontiguousarray(system["b"], dtype=np.float32).reshape(-1)
+        n = self.b.size // d
+        prob = system.get("prob")
+        self.prob = None if prob is None else np.ascontiguousarray(prob, dtype=np.float64)
+        fp = np.zeros(24, np.float32)
+        src = np.asarray(system.get("final_params", []), np.float32).reshape(-1)
+        fp[: src.size] = src
+        self.fp = fp
+        self.s = _System(d, n, self.A.ctypes.data_as(C.POINTER(C.c_float)),
+                         self.b.ctypes.data_as(C.POINTER(C.c_float)),
+                         None if self.prob is None else
+                         self.prob.ctypes.data_as(C.POINTER(C.c_double)),
+                         FINAL_KINDS[system.get("final_kind", "identity")],
+                         self.fp.ctypes.data_as(C.POINTER(C.c_float)))
+
+
+def _run(run):
+    return _Run(int(run.get("seed", 0)), int(run.get("instance", 0)),
+                int(run["n_points"]), int(run.get("point_offset", 0)),
+                int(run["n_iters"]), int(run["burn_in"]))
+
+
+def _window(img):
+    lo = (C.c_float * 2)(*[float(v) for v in img["lo"]])
+    hi = (C.c_float * 2)(*[float(v) for v in img["hi"]])
+    return _Window(int(img["width"]), int(img["height"]),
+                   int(img.get("channels", 1)), lo, hi)
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise ValueError(f"oracle {name} rejected its arguments (rc={rc})")
+
+
+# --------------------------------------------------------------------------
+# Public oracle functions (numpy in, numpy out)
+# --------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block for a 4-word counter and a 2-word key."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib.orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def philox_many(seed, ctrs):
+    """Philox blocks for an [n, 4] array of counters under one 64-bit seed."""
+    lib = _load()
+    c = np.ascontiguousarray(ctrs, dtype=np.uint32).reshape(-1, 4)
+    out = np.zeros_like(c)
+    lib.orc_philox_many(C.c_uint64(seed), _ptr(c), _ptr(out), c.shape[0])
+    return out
+
+
+def thresholds(prob, n):
+    lib = _load()
+    out = np.zeros(n, np.uint64)
+    p = None if prob is None else np.ascontiguousarray(prob, dtype=np.float64)
+    _check(lib.orc_thresholds(_ptr(p), n, _ptr(out)), "thresholds")
+    return out
+
+
+def select(u, thresh):
+    lib = _load()
+    t = np.ascontiguousarray(thresh, dtype=np.uint64)
+    return int(lib.orc_select(C.c_uint32(int(u)), _ptr(t), t.size))
+
+
+def select_histogram(thresh):
+    """Counts of every index over all 2^32 draws (exhaustive, a few seconds)."""
+    lib = _load()
+    t = np.ascontiguousarray(thresh, dtype=np.uint64)
+    out = np.zeros(t.size, np.uint64)
+    lib.orc_select_histogram(_ptr(t), t.size, _ptr(out))
+    return out
+
+
+def chaos_count(system, run, image, *, want_final=False, want_last=False,
+                want_indices=False, want_splats=False, out=None):
+    """Plain chaos game with a u32 count image [channels][H][W].
+
+    Returns a dict with 'image' (accumulated into ``out`` when given) and the
+    optional 'final' [N][dim] (FP64), 'last' [N], 'indices' [N][T],
+    'splats' [N][T-B][2] fractional pixel coordinates, and 'dropped'.
+    """
+    lib = _load()
+    keep = _Keep(system)
+    r = _run(run)
+    w = _window(image)
+    N, T, B, d = r.n_points, r.n_iters, r.burn_in, keep.s.dim
+    img = out if out is not None else np.zeros(
+        (w.channels, w.height, w.width), np.uint32)
+    assert img.dtype == np.uint32 and img.flags.c_contiguous
+    fin = np.zeros((N, d), np.float64) if want_final else None
+    last = np.zeros(N, np.uint8) if want_last else None
+    idx = np.zeros((N, T), np.uint8) if want_indices else None
+    spl = np.zeros((N, T - B, 2), np.float64) if want_splats else None
+    dropped = np.zeros(1, np.uint64)
+    rc = lib.orc_chaos_count(C.byref(keep.s), C.byref(r), C.byref(w), _ptr(img),
+                             _ptr(fin), _ptr(last), _ptr(idx), _ptr(spl),
+                             _ptr(dropped))
+    _check(rc, "chaos_count")
+    return {"image": img, "final": fin, "last": last, "indices": idx,
+            "splats": spl, "dropped": int(dropped[0])}
+
+
+def chaos_depth(system, run, image, near, *, want_final=False, want_last=False,
+                want_splats=False, depth=None, density=None):
+    """3D chaos game into a u64 depth|index min-buffer and a u32 density."""
+    lib = _load()
+    keep = _Keep(system)
+    r = _run(run)
+    w = _window(image)
+    N, T, B = r.n_points, r.n_iters, r.burn_in
+    if depth is None:
+        depth = np.full((w.height, w.width), np.iinfo(np.uint64).max, np.uint64)
+    if density is None:
+        density = np.zeros((w.height, w.width), np.uint32)
+    fin = np.zeros((N, 3), np.float64) if want_final else None
+    last = np.zeros(N, np.uint8) if want_last else None
+    spl = np.zeros((N, T - B, 3), np.float64) if want_splats else None
+    dropped = np.zeros(1, np.uint64)
+    rc = lib.orc_chaos_depth(C.byref(keep.s), C.byref(r), C.byref(w),
+                             C.c_float(near), _ptr(depth), _ptr(density),
+                             _ptr(fin), _ptr(last), _ptr(spl), _ptr(dropped))
+    _check(rc, "chaos_depth")
+    return {"depth": depth, "density": density, "final": fin, "last": last,
+            "splats": spl, "dropped": int(dropped[0])}
+
+
+def splat_gauss(system, run, image, sigma_px, *, want_final=False):
+    """FP64 Gaussian soft-splat density [H][W] (sum of weights / (N (T-B)))."""
+    lib = _load()
+    keep = _Keep(system)
+    r = _run(run)
+    w = _window(image)
+    dens = np.zeros((w.height, w.width), np.float64)
+    fin = np.zeros((r.n_points, 2), np.float64) if want_final else None
+    rc = lib.orc_splat_gauss(C.byref(keep.s), C.byref(r), C.byref(w),
+                             C.c_double(sigma_px), _ptr(dens), _ptr(fin))
+    _check(rc, "splat_gauss")
+    return dens if not want_final else (dens, fin)
+
+
+def splat_gauss_backward(system, run, image, sigma_px, dL_dD):
+    """Gradient of L w.r.t. the maps, [n_maps][6] = (a00,a01,a10,a11,b0,b1)."""
+    lib = _load()
+    keep = _Keep(system)
+    r = _run(run)
+    w = _window(image)
+    g = np.ascontiguousarray(dL_dD, dtype=np.float64)
+    assert g.shape == (w.height, w.width)
+    grad = np.zeros((keep.s.n_maps, 6), np.float64)
+    rc = lib.orc_splat_gauss_backward(C.byref(keep.s), C.byref(r), C.byref(w),
+                                      C.c_double(sigma_px), _ptr(g), _ptr(grad))
+    _check(rc, "splat_gauss_backward")
+    return grad
+
+
+def gauss_loss(system, run, image, sigma_px, target):
+    """L = sum (D - D*)^2 with D from splat_gauss."""
+    D = splat_gauss(system, run, image, sigma_px)
+    return float(np.sum((D - target) ** 2)), D
