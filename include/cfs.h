@@ -1,0 +1,258 @@
+/*
+ * cfs.h -- C ABI of the MI355X (gfx950) chaos-game library for composable
+ * function systems (CFS).
+ *
+ * What the library computes (Schloss, "Composable function systems as a
+ * general-purpose rendering framework"):
+ *   - Section 1, Section 3 (opening): the chaos game.  Many independent points
+ *     each start at a random position; every step a point picks one function
+ *     of the system at random, applies it, and is then histogrammed (splatted)
+ *     onto the output image.
+ *   - Section 1 (fig. "workflow"): splats may be coloured by the index of the
+ *     function that moved the point.
+ *   - Section 3 (fig. "circle" B) and the caption of fig. "workflow": a
+ *     composed spatial transform acts on a COPY of the point before it is
+ *     splatted; the original keeps iterating.
+ *   - Section 1: only the output image and a few bytes of function arguments
+ *     live in device memory; no point cloud is stored.
+ *   - Section 4 (limitations): density estimation needs atomic operations;
+ *     automatic generation of the primitive's distribution is suggested with
+ *     tools similar to automatic differentiation -- the Gaussian splat and
+ *     its adjoint below are that differentiable form.
+ *
+ * Conventions shared by every entry point
+ *   - Host structs are read only during the call; everything the GPU needs
+ *     is copied into kernel arguments or into library-owned device memory.
+ *   - Every device pointer is owned by the caller and must stay valid until
+ *     the work enqueued on `stream` has finished.  `stream` is a hipStream_t
+ *     passed as void*; NULL means the default stream of the current device.
+ *   - Work is enqueued asynchronously on `stream`; results are visible after
+ *     the caller synchronises that stream.
+ *   - Every argument is validated on the host before anything is enqueued:
+ *     on error nothing is written and a negative CFS_E_* code is returned;
+ *     cfs_last_error() then describes the problem (thread-local string).
+ *     Asynchronous device faults surface as CFS_E_DEVICE from a later call.
+ *   - Images are planar, row-major: [channels][height][width]; row 0 is at
+ *     lo[1], column 0 at lo[0].  A point q lands in pixel
+ *     (floor((q.x - lo.x) W / (hi.x - lo.x)), floor((q.y - lo.y) H / (hi.y - lo.y)))
+ *     if both are inside [0, W) x [0, H); otherwise (or if NaN) it is dropped.
+ *   - Random streams: Philox4x32-10 (Salmon et al., SC'11) with key
+ *     (seed low word, seed high word) and counter (global point id, block,
+ *     instance, tag).  Tag 1 block 0 gives the initial point, one 24-bit
+ *     word per coordinate on the 2^-24 grid of [0,1)^dim; tag 0 block j gives
+ *     the four draws of iterations 4j+1 .. 4j+4.  The draw u of an iteration
+ *     selects map k = min{ i : u < thresh[i] } with thresh[i] =
+ *     ceil(2^32 P_i) for the FP64 cumulative probabilities P_i (last = 2^32),
+ *     or thresh[i] = ceil((i+1) 2^32 / n) when prob is NULL.  Because the
+ *     streams are keyed by global point id, runs split by point ranges add up
+ *     exactly to the whole run.
+ */
+#ifndef CFS_H
+#define CFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFS_VERSION 1
+
+/* Status codes. */
+#define CFS_OK 0
+#define CFS_E_INVALID (-1)     /* an argument failed validation */
+#define CFS_E_UNSUPPORTED (-2) /* valid but not implemented combination */
+#define CFS_E_NOMEM (-3)       /* a library-owned allocation failed */
+#define CFS_E_DEVICE (-4)      /* the HIP runtime reported an error */
+#define CFS_E_WORKSPACE (-5)   /* workspace missing or too small */
+
+#define CFS_MAX_MAPS 64
+
+/* Composed transform applied to the copy of the point before splatting. */
+enum {
+  CFS_FINAL_IDENTITY = 0,     /* q = (p.x, p.y) */
+  CFS_FINAL_SWIRL = 1,        /* 2D, params {cx, cy, kappa, tx, ty}:
+                                 d = p - c, r = |d|, q = c + t + R(kappa r) d */
+  CFS_FINAL_TWIST_CAMERA = 2, /* 3D, params {kappa, cx, cy, cz, M[12], fx, fy}:
+                                 w = p - c twisted about the vertical axis by
+                                 kappa w.y, v = M[:, :3] w + M[:, 3],
+                                 q = (fx v.x / v.z, fy v.y / v.z), depth v.z */
+  CFS_FINAL_STRETCH = 3       /* 2D, params {sx, sy}: q = (sx x, y - sy cos x)
+                                 (Section 3's stretch is sx = 2, sy = 1) */
+};
+
+/* Image element types. */
+enum {
+  CFS_IMAGE_U32_COUNT = 0,   /* uint32 [channels][H][W]; channels 1 or n_maps
+                                (then channel = index of the last map) */
+  CFS_IMAGE_F32_DENSITY = 1, /* float  [H][W] */
+  CFS_IMAGE_U64_DEPTH = 2    /* uint64 [H][W] min of (float bits of depth) << 32
+                                | map index, plus uint32 density [H][W] */
+};
+
+/* Arithmetic type of the point positions and transforms on the GPU. */
+enum { CFS_PREC_F32 = 0, CFS_PREC_F64 = 1 };
+
+/* A function system: n affine maps p -> A_k p + b_k and a composed transform.
+ * The map table is copied into kernel arguments (a few KiB at most). */
+typedef struct cfs_system {
+  int32_t dim;            /* 2 or 3 */
+  int32_t n_maps;         /* 1 .. CFS_MAX_MAPS */
+  const float *A;         /* host [n_maps][dim][dim], row-major */
+  const float *b;         /* host [n_maps][dim] */
+  const double *prob;     /* host [n_maps] summing to 1 (+-1e-6), or NULL */
+  int32_t final_kind;     /* CFS_FINAL_* */
+  float final_params[24]; /* meaning per final_kind, unused entries ignored */
+} cfs_system;
+
+/* One run over a range of points. */
+typedef struct cfs_run {
+  uint64_t seed;          /* Philox key */
+  uint32_t instance;      /* third counter word (batched instance id) */
+  uint32_t n_points;      /* N */
+  uint32_t point_offset;  /* global id of the first point; offset + N <= 2^32 */
+  uint32_t n_iters;       /* T map applications per point, 1 .. 2^20 */
+  uint32_t burn_in;       /* B <= T: iterations 1..B are not splatted */
+  int32_t precision;      /* CFS_PREC_F32 or CFS_PREC_F64 */
+} cfs_run;
+
+/* An output image in device memory. */
+typedef struct cfs_image {
+  int32_t kind;           /* CFS_IMAGE_* */
+  int32_t width, height;  /* 1 .. 65536 each; W*H*channels <= 2^31 */
+  int32_t channels;       /* 1, or n_maps for per-index counts */
+  float lo[2], hi[2];     /* window, lo < hi */
+  float near_plane;       /* depth images: splats with depth <= near dropped */
+  void *data;             /* device, element type per kind (see above) */
+  uint32_t *density;      /* device uint32 [H][W], CFS_IMAGE_U64_DEPTH only */
+  unsigned long long *dropped; /* device counter of dropped splats, or NULL */
+} cfs_image;
+
+/* Library version (CFS_VERSION). */
+int cfs_version(void);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *cfs_last_error(void);
+
+/* Image initialisation (the image is the method's only global allocation,
+ * Section 1): counts and densities to 0, depth keys to all ones, density of a
+ * depth image to 0, and *dropped to 0.  Enqueued on `stream`. */
+int cfs_image_clear(const cfs_image *img, void *stream);
+
+/* Workspace in bytes that cfs_chaos_game needs for this system, run and
+ * image (0 when the direct-atomic splat is used).  Returns 0 on invalid
+ * arguments as well; cfs_chaos_game then reports the error. */
+size_t cfs_chaos_game_workspace(const cfs_system *sys, const cfs_run *run,
+                                const cfs_image *img);
+
+/* The plain chaos game with an integer splat (Section 1, Section 3):
+ * for each of run->n_points points, iterate run->n_iters maps chosen from
+ * the point's own random stream and, after burn-in, splat the transformed
+ * copy (final_kind) into `img`, which ACCUMULATES (the caller clears it,
+ * e.g. with cfs_image_clear), so point-range splits compose exactly.
+ *   img->kind CFS_IMAGE_U32_COUNT: +1 per splat (channel = last map index
+ *     when channels == n_maps); CFS_IMAGE_U64_DEPTH (3D, TWIST_CAMERA):
+ *     atomic min of the depth|index key and +1 in img->density.
+ *   final_points: device, nullable; [n_points][dim] of float (F32) or
+ *     double (F64): each point's position after n_iters steps.
+ *   last_index:   device, nullable; uint8 [n_points]: index of the last map.
+ *   indices:      device, nullable; uint8 [n_points][n_iters]: every index.
+ *   workspace:    device scratch of cfs_chaos_game_workspace() bytes (may be
+ *     NULL when that is 0); contents need no initialisation.
+ * Returns CFS_OK or a negative CFS_E_* code (nothing enqueued on error). */
+int cfs_chaos_game(const cfs_system *sys, const cfs_run *run,
+                   const cfs_image *img, void *final_points,
+                   uint8_t *last_index, uint8_t *indices, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
+/* Differentiable form, forward (Section 4: automatic generation of the
+ * primitive's distribution with autodiff-like tools): the chaos game of a 2D
+ * affine system with the identity transform, splatted with the separable
+ * shifted-truncated Gaussian g(d) = exp(-d^2/2s^2) - exp(-9/2) for |d| < 3s
+ * (s = sigma_px, d = pixel centre - point, in pixels) into an FP32 density
+ * img (kind CFS_IMAGE_F32_DENSITY) that ACCUMULATES sum(w) / (N (T - B)).
+ *   ckpt: device, nullable; float [n_iters / ckpt_every + 1][n_points][2]:
+ *     positions at iterations 0, c, 2c, ... (c = ckpt_every >= 1) that the
+ *     backward pass recomputes its segments from.
+ * Supports sigma_px in (0, 2.5] (at most 16 taps per axis). */
+int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
+              float sigma_px, float *ckpt, int32_t ckpt_every, void *stream);
+
+/* Workspace in bytes for cfs_splat_backward. */
+size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run);
+
+/* Differentiable form, adjoint: given dL/dD (device float [H][W], the
+ * upstream gradient of the density that cfs_splat produced) and that call's
+ * checkpoints, recompute each trajectory segment and run the adjoint
+ *   lam_T = s_T, lam_t = s_t + A_{k_{t+1}}^T lam_{t+1},
+ *   dL/dA_{k_t} += lam_t p_{t-1}^T, dL/db_{k_t} += lam_t
+ * (s_t = dL/dp_t through the splat of step t).  grad (device float
+ * [n_maps][6] = a00 a01 a10 a11 b0 b1) is OVERWRITTEN; the reduction is
+ * deterministic (fixed order, no floating-point atomics).
+ * ckpt may be NULL: segments are then recomputed from the initial points. */
+int cfs_splat_backward(const cfs_system *sys, const cfs_run *run,
+                       const cfs_image *img, float sigma_px,
+                       const float *dL_dD, const float *ckpt,
+                       int32_t ckpt_every, float *grad, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/* Batched form: many heterogeneous systems (animation frames, different map
+ * counts, point counts and image sizes) rendered by ONE persistent kernel
+ * launch captured in a HIP graph.  Each instance renders exactly what
+ * cfs_chaos_game renders for it (same streams, same device functions). */
+typedef struct cfs_batch_item {
+  cfs_system sys;  /* 2D, identity transform, up to CFS_MAX_MAPS maps */
+  cfs_run run;     /* run.instance selects the instance's random streams */
+  cfs_image img;   /* CFS_IMAGE_U32_COUNT, one channel, caller-owned data */
+} cfs_batch_item;
+
+/* Schedule of a batch: chunk = points per work item; block = threads per
+ * workgroup; grid = persistent workgroups (0 = one per compute unit times
+ * the occupancy); lds_limit = largest image (pixels) rendered through an
+ * LDS-private tile (0 = never). */
+typedef struct cfs_plan {
+  int32_t chunk;
+  int32_t block;
+  int32_t grid;
+  int32_t lds_limit;
+} cfs_plan;
+
+typedef struct cfs_batch cfs_batch; /* opaque, library-owned */
+
+/* Build a batch: copies the descriptors into library-owned device memory
+ * and plans the work queue.  plan NULL = autotuned defaults.  The images
+ * are cleared by every cfs_batch_run. */
+int cfs_batch_create(const cfs_batch_item *items, int32_t n_items,
+                     const cfs_plan *plan, cfs_batch **out);
+
+/* Enqueue the whole batch on `stream`: the first call captures {clear the
+ * images, reset the work queue, persistent kernel} into a HIP graph; later
+ * calls replay it. */
+int cfs_batch_run(cfs_batch *batch, void *stream);
+
+/* Replace instance `index`'s system (same map count; e.g. the next
+ * animation frame) without re-capturing the graph.  Ordered on `stream`. */
+int cfs_batch_update(cfs_batch *batch, int32_t index, const cfs_system *sys,
+                     void *stream);
+
+/* The plan a batch uses. */
+int cfs_batch_plan(const cfs_batch *batch, cfs_plan *out);
+
+void cfs_batch_destroy(cfs_batch *batch);
+
+/* Project-written autotuner: times candidate plans for this batch with HIP
+ * events on `stream` and writes the fastest to *out. */
+int cfs_autotune(const cfs_batch_item *items, int32_t n_items, cfs_plan *out,
+                 void *stream);
+
+/* Parity hook: out[i] = Philox4x32-10(ctrs[i], key(seed)) for i < n.
+ * ctrs, out: device uint32 [n][4]. */
+int cfs_philox_dump(uint64_t seed, const uint32_t *ctrs, uint32_t *out,
+                    uint64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFS_H */

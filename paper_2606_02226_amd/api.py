@@ -1,0 +1,151 @@
+"""Python binding of the CFS chaos-game library (argument marshalling only).
+
+Every step of the path runs in the HIP kernels of libcfs.so; this module turns
+workload dicts and torch tensors into the C structs of include/cfs.h and
+passes device pointers plus the current HIP stream.  PyTorch provides device
+memory and streams, nothing else.
+
+Workload dicts (see ``workloads``) carry:
+  system: dim, A [n][d][d], b [n][d], prob or None, final_kind, final_params
+  run:    seed, instance, n_points, point_offset, n_iters, burn_in
+  image:  kind, width, height, channels, lo, hi (and near for depth images)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CfsImage, CfsRun, CfsSystem, check
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class System:
+    """C view of a system dict; keeps the host arrays alive."""
+
+    def __init__(self, system):
+        d = int(system["dim"])
+        self.A = np.ascontiguousarray(system["A"], dtype=np.float32).reshape(-1)
+        self.b = np.ascontiguousarray(system["b"], dtype=np.float32).reshape(-1)
+        n = self.b.size // d
+        prob = system.get("prob")
+        self.prob = None if prob is None else np.ascontiguousarray(prob, np.float64)
+        fp = (C.c_float * 24)()
+        src = np.asarray(system.get("final_params", []), np.float32).reshape(-1)
+        for i, v in enumerate(src[:24]):
+            fp[i] = float(v)
+        self.struct = CfsSystem(
+            d, n, self.A.ctypes.data_as(C.POINTER(C.c_float)),
+            self.b.ctypes.data_as(C.POINTER(C.c_float)),
+            None if self.prob is None else self.prob.ctypes.data_as(C.POINTER(C.c_double)),
+            _lib.FINAL_KINDS[system.get("final_kind", "identity")], fp)
+        self.dim, self.n_maps = d, n
+
+
+def run_struct(run, precision="f32"):
+    return CfsRun(int(run.get("seed", 0)), int(run.get("instance", 0)),
+                  int(run["n_points"]), int(run.get("point_offset", 0)),
+                  int(run["n_iters"]), int(run["burn_in"]),
+                  _lib.PRECISIONS[precision])
+
+
+class Image:
+    """Device image of a workload's image description.
+
+    u32_count: int32 storage [channels][H][W] (read back as uint32);
+    f32_density: float32 [H][W]; u64_depth: int64 keys [H][W] (read back as
+    uint64) plus int32 density [H][W].  ``dropped`` counts dropped splats.
+    """
+
+    def __init__(self, desc, device="cuda", data=None):
+        self.desc = dict(desc)
+        kind = desc["kind"]
+        W, H, Ch = int(desc["width"]), int(desc["height"]), int(desc.get("channels", 1))
+        self.kind = kind
+        self.density = None
+        if data is not None:
+            self.data = data
+        elif kind == "u32_count":
+            self.data = torch.empty((Ch, H, W), dtype=torch.int32, device=device)
+        elif kind == "f32_density":
+            self.data = torch.empty((H, W), dtype=torch.float32, device=device)
+        elif kind == "u64_depth":
+            self.data = torch.empty((H, W), dtype=torch.int64, device=device)
+        else:
+            raise ValueError(f"unknown image kind {kind}")
+        if kind == "u64_depth":
+            self.density = torch.empty((H, W), dtype=torch.int32, device=device)
+        self.dropped = torch.zeros(1, dtype=torch.int64, device=device)
+        lo = (C.c_float * 2)(*[float(v) for v in desc["lo"]])
+        hi = (C.c_float * 2)(*[float(v) for v in desc["hi"]])
+        self.struct = CfsImage(_lib.IMAGE_KINDS[kind], W, H, Ch, lo, hi,
+                               float(desc.get("near", 0.0)), self.data.data_ptr(),
+                               None if self.density is None else self.density.data_ptr(),
+                               self.dropped.data_ptr())
+
+    def clear(self, stream=None):
+        check(_lib.load().cfs_image_clear(C.byref(self.struct), _stream_handle(stream)),
+              "cfs_image_clear")
+        return self
+
+    def to_numpy(self):
+        """Host copies with the element types of include/cfs.h."""
+        torch.cuda.synchronize()
+        out = {"dropped": int(self.dropped.cpu().item())}
+        a = self.data.cpu().numpy()
+        if self.kind == "u32_count":
+            out["image"] = a.view(np.uint32)
+        elif self.kind == "u64_depth":
+            out["depth"] = a.view(np.uint64)
+            out["density"] = self.density.cpu().numpy().view(np.uint32)
+        else:
+            out["image"] = a
+        return out
+
+
+def image_clear(image, stream=None):
+    return image.clear(stream)
+
+
+def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
+               indices=None, stream=None):
+    """Enqueue the plain chaos game (cfs_chaos_game) into ``image``.
+
+    ``system`` is a workload system dict or a :class:`System`; ``final``
+    (float32/float64 [N][dim]), ``last`` (uint8 [N]) and ``indices``
+    (uint8 [N][T]) are optional device tensors.  The image accumulates.
+    """
+    lib = _lib.load()
+    sysc = system if isinstance(system, System) else System(system)
+    runc = run_struct(run, precision)
+    ws_bytes = lib.cfs_chaos_game_workspace(C.byref(sysc.struct), C.byref(runc),
+                                            C.byref(image.struct))
+    ws = None
+    if ws_bytes:
+        ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device=image.data.device)
+    rc = lib.cfs_chaos_game(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
+                            _ptr(final), _ptr(last), _ptr(indices), _ptr(ws),
+                            C.c_size_t(ws_bytes), _stream_handle(stream))
+    check(rc, "cfs_chaos_game")
+    return image
+
+
+def philox_dump(seed, ctrs, stream=None):
+    """Philox4x32-10 blocks of an int32/uint32 device tensor [n][4] of counters."""
+    lib = _lib.load()
+    ctrs = ctrs.contiguous()
+    out = torch.empty_like(ctrs)
+    check(lib.cfs_philox_dump(C.c_uint64(int(seed)), _ptr(ctrs), _ptr(out),
+                              C.c_uint64(ctrs.shape[0]), _stream_handle(stream)),
+          "cfs_philox_dump")
+    return out

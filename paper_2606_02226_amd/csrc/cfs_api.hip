@@ -1,0 +1,299 @@
+// cfs_api.hip -- the C ABI (include/cfs.h): host-side validation, packing of
+// the map table into kernel arguments, dispatch to the kernels, and error
+// reporting through a thread-local message.  Every argument is checked
+// before anything is enqueued, so a failed call writes nothing.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "cfs.h"
+#include "cfs_api_internal.hpp"
+#include "cfs_host.hpp"
+
+namespace cfs {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int device_status(hipError_t e, const char *what) {
+  if (e == hipSuccess) return CFS_OK;
+  return fail(CFS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Selection thresholds (the library's own computation; the paper does not
+// fix a rule): thresh[i] = ceil(2^32 P_i) for the FP64 left-to-right
+// cumulative probabilities, or ceil((i+1) 2^32 / n) for equal ones; the last
+// threshold is 2^32.
+int make_thresholds(const double *prob, int n, uint64_t *thresh) {
+  const uint64_t two32 = 1ull << 32;
+  if (!prob) {
+    for (int i = 0; i < n; ++i)
+      thresh[i] = ((static_cast<uint64_t>(i) + 1) * two32 + static_cast<uint64_t>(n - 1)) /
+                  static_cast<uint64_t>(n);
+    return CFS_OK;
+  }
+  double cum = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(prob[i]) || prob[i] < 0.0)
+      return fail(CFS_E_INVALID, "prob[%d] = %g is not a finite non-negative number", i, prob[i]);
+    cum += prob[i];
+    const double scaled = std::ceil(std::ldexp(cum, 32));
+    thresh[i] = scaled >= std::ldexp(1.0, 32) ? two32 : static_cast<uint64_t>(scaled);
+  }
+  if (std::fabs(cum - 1.0) > 1e-6)
+    return fail(CFS_E_INVALID, "probabilities sum to %.9g, not 1", cum);
+  thresh[n - 1] = two32;
+  return CFS_OK;
+}
+
+int validate_system(const cfs_system *s) {
+  if (!s) return fail(CFS_E_INVALID, "system is NULL");
+  if (s->dim != 2 && s->dim != 3) return fail(CFS_E_INVALID, "dim must be 2 or 3 (got %d)", s->dim);
+  if (s->n_maps < 1 || s->n_maps > CFS_MAX_MAPS)
+    return fail(CFS_E_INVALID, "n_maps must be in 1..%d (got %d)", CFS_MAX_MAPS, s->n_maps);
+  if (!s->A || !s->b) return fail(CFS_E_INVALID, "map table A/b is NULL");
+  const int d = s->dim;
+  for (int i = 0; i < s->n_maps * d * d; ++i)
+    if (!std::isfinite(s->A[i])) return fail(CFS_E_INVALID, "A[%d] is not finite", i);
+  for (int i = 0; i < s->n_maps * d; ++i)
+    if (!std::isfinite(s->b[i])) return fail(CFS_E_INVALID, "b[%d] is not finite", i);
+  for (int i = 0; i < 24; ++i)
+    if (!std::isfinite(s->final_params[i]))
+      return fail(CFS_E_INVALID, "final_params[%d] is not finite", i);
+  switch (s->final_kind) {
+    case CFS_FINAL_IDENTITY: break;
+    case CFS_FINAL_SWIRL:
+    case CFS_FINAL_STRETCH:
+      if (d != 2) return fail(CFS_E_INVALID, "final kind %d needs dim 2", s->final_kind);
+      break;
+    case CFS_FINAL_TWIST_CAMERA:
+      if (d != 3) return fail(CFS_E_INVALID, "twist/camera transform needs dim 3");
+      break;
+    default: return fail(CFS_E_INVALID, "unknown final kind %d", s->final_kind);
+  }
+  uint64_t th[CFS_MAX_MAPS];
+  return make_thresholds(s->prob, s->n_maps, th);
+}
+
+int validate_run(const cfs_run *r) {
+  if (!r) return fail(CFS_E_INVALID, "run is NULL");
+  if (r->n_iters < 1 || r->n_iters > (1u << 20))
+    return fail(CFS_E_INVALID, "n_iters must be in 1..2^20 (got %u)", r->n_iters);
+  if (r->burn_in > r->n_iters)
+    return fail(CFS_E_INVALID, "burn_in %u exceeds n_iters %u", r->burn_in, r->n_iters);
+  if (static_cast<uint64_t>(r->point_offset) + r->n_points > (1ull << 32))
+    return fail(CFS_E_INVALID, "point_offset + n_points exceeds 2^32");
+  if (r->precision != CFS_PREC_F32 && r->precision != CFS_PREC_F64)
+    return fail(CFS_E_INVALID, "precision must be CFS_PREC_F32 or CFS_PREC_F64");
+  return CFS_OK;
+}
+
+int validate_window(const cfs_image *img) {
+  if (!img) return fail(CFS_E_INVALID, "image is NULL");
+  if (img->width < 1 || img->width > 65536 || img->height < 1 || img->height > 65536)
+    return fail(CFS_E_INVALID, "image size %dx%d outside 1..65536", img->width, img->height);
+  if (img->channels < 1) return fail(CFS_E_INVALID, "channels must be >= 1");
+  const uint64_t total = static_cast<uint64_t>(img->width) * img->height * img->channels;
+  if (total > (1ull << 31)) return fail(CFS_E_INVALID, "image holds more than 2^31 elements");
+  for (int a = 0; a < 2; ++a) {
+    if (!std::isfinite(img->lo[a]) || !std::isfinite(img->hi[a]) || !(img->hi[a] > img->lo[a]))
+      return fail(CFS_E_INVALID, "window axis %d needs finite lo < hi", a);
+  }
+  if (!img->data) return fail(CFS_E_INVALID, "image data is NULL");
+  const size_t align = img->kind == CFS_IMAGE_U64_DEPTH ? 8 : 4;
+  if (reinterpret_cast<uintptr_t>(img->data) % align)
+    return fail(CFS_E_INVALID, "image data is not %zu-byte aligned", align);
+  if (img->kind == CFS_IMAGE_U64_DEPTH) {
+    if (!img->density) return fail(CFS_E_INVALID, "depth image needs a density buffer");
+    if (reinterpret_cast<uintptr_t>(img->density) % 4)
+      return fail(CFS_E_INVALID, "density is not 4-byte aligned");
+    if (img->channels != 1) return fail(CFS_E_INVALID, "depth image has one channel");
+  }
+  if (img->dropped && reinterpret_cast<uintptr_t>(img->dropped) % 8)
+    return fail(CFS_E_INVALID, "dropped counter is not 8-byte aligned");
+  return CFS_OK;
+}
+
+Window make_window(const cfs_image *img, bool by_index) {
+  Window w{};
+  w.width = img->width;
+  w.height = img->height;
+  w.channels = img->channels;
+  w.by_index = by_index ? 1 : 0;
+  for (int a = 0; a < 2; ++a) {
+    w.lo[a] = static_cast<double>(img->lo[a]);
+    const double extent = static_cast<double>(img->hi[a]) - static_cast<double>(img->lo[a]);
+    w.scale[a] = static_cast<double>(a == 0 ? img->width : img->height) / extent;
+  }
+  return w;
+}
+
+RunArgs make_run_args(const cfs_run *r) {
+  RunArgs ra{};
+  ra.k0 = static_cast<uint32_t>(r->seed);
+  ra.k1 = static_cast<uint32_t>(r->seed >> 32);
+  ra.instance = r->instance;
+  ra.n_points = r->n_points;
+  ra.point_offset = r->point_offset;
+  ra.n_iters = r->n_iters;
+  ra.burn_in = r->burn_in;
+  return ra;
+}
+
+template <int DIM>
+int pack_table(const cfs_system *s, MapTable<DIM> *mt, bool *equal) {
+  std::memset(mt, 0, sizeof *mt);
+  const int n = s->n_maps;
+  constexpr int C = DIM * (DIM + 1);
+  for (int m = 0; m < n; ++m) {
+    for (int r = 0; r < DIM; ++r) {
+      for (int c = 0; c < DIM; ++c) mt->coef[m * C + r * DIM + c] = s->A[(m * DIM + r) * DIM + c];
+      mt->coef[m * C + DIM * DIM + r] = s->b[m * DIM + r];
+    }
+  }
+  mt->n_maps = n;
+  uint64_t th[CFS_MAX_MAPS];
+  const int rc = make_thresholds(s->prob, n, th);
+  if (rc) return rc;
+  *equal = (s->prob == nullptr);
+  if (*equal) {
+    mt->n_search = 0;
+    mt->top_step = 0;
+    return CFS_OK;
+  }
+  // maps past the first threshold that reaches 2^32 can never be drawn
+  int ns = n;
+  for (int i = 0; i < n; ++i)
+    if (th[i] >= (1ull << 32)) {
+      ns = i + 1;
+      break;
+    }
+  for (int i = 0; i < ns - 1; ++i) mt->thresh[i] = static_cast<uint32_t>(th[i]);
+  mt->n_search = ns;
+  int step = 0;
+  if (ns > 1) {
+    step = 1;
+    while (step * 2 <= ns - 1) step *= 2;
+  }
+  mt->top_step = step;
+  return CFS_OK;
+}
+
+template int pack_table<2>(const cfs_system *, MapTable<2> *, bool *);
+template int pack_table<3>(const cfs_system *, MapTable<3> *, bool *);
+
+}  // namespace cfs
+
+using namespace cfs;
+
+extern "C" int cfs_version(void) { return CFS_VERSION; }
+
+extern "C" const char *cfs_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int cfs_image_clear(const cfs_image *img, void *stream) {
+  clear_error();
+  int rc = validate_window(img);
+  if (rc) return rc;
+  const size_t n = static_cast<size_t>(img->width) * img->height * img->channels;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  switch (img->kind) {
+    case CFS_IMAGE_U32_COUNT:
+    case CFS_IMAGE_F32_DENSITY:  // +0.0f has the all-zero bit pattern
+      e = launch_clear_u32(static_cast<uint32_t *>(img->data), n, s);
+      break;
+    case CFS_IMAGE_U64_DEPTH:
+      e = launch_fill_u64(static_cast<unsigned long long *>(img->data), n, ~0ull, s);
+      if (e == hipSuccess) e = launch_clear_u32(img->density, n, s);
+      break;
+    default: return fail(CFS_E_INVALID, "unknown image kind %d", img->kind);
+  }
+  if (e == hipSuccess && img->dropped) e = launch_fill_u64(img->dropped, 1, 0ull, s);
+  return device_status(e, "cfs_image_clear");
+}
+
+extern "C" size_t cfs_chaos_game_workspace(const cfs_system *sys, const cfs_run *run,
+                                           const cfs_image *img) {
+  (void)sys;
+  (void)run;
+  (void)img;
+  return 0;
+}
+
+extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
+                              void *final_points, uint8_t *last_index, uint8_t *indices,
+                              void *workspace, size_t workspace_bytes, void *stream) {
+  clear_error();
+  int rc = validate_system(sys);
+  if (!rc) rc = validate_run(run);
+  if (!rc) rc = validate_window(img);
+  if (rc) return rc;
+  (void)workspace;
+  (void)workspace_bytes;
+  ChaosJob job;
+  std::memset(&job, 0, sizeof job);
+  job.dim = sys->dim;
+  job.final_kind = sys->final_kind;
+  job.precision = run->precision;
+  if (img->kind == CFS_IMAGE_U32_COUNT) {
+    if (sys->final_kind == CFS_FINAL_TWIST_CAMERA)
+      return fail(CFS_E_UNSUPPORTED, "the camera transform renders into a U64 depth image");
+    if (img->channels != 1 && img->channels != sys->n_maps)
+      return fail(CFS_E_INVALID, "channels must be 1 or n_maps (%d), got %d", sys->n_maps,
+                  img->channels);
+    job.depth = false;
+  } else if (img->kind == CFS_IMAGE_U64_DEPTH) {
+    if (sys->final_kind != CFS_FINAL_TWIST_CAMERA)
+      return fail(CFS_E_UNSUPPORTED, "a depth image needs the twist/camera transform");
+    if (!std::isfinite(img->near_plane))
+      return fail(CFS_E_INVALID, "near_plane is not finite");
+    job.depth = true;
+  } else {
+    return fail(CFS_E_INVALID, "cfs_chaos_game renders U32_COUNT or U64_DEPTH images");
+  }
+  const size_t align = run->precision == CFS_PREC_F64 ? 8 : 4;
+  if (final_points && reinterpret_cast<uintptr_t>(final_points) % align)
+    return fail(CFS_E_INVALID, "final_points is not %zu-byte aligned", align);
+  if (sys->dim == 2)
+    rc = pack_table<2>(sys, &job.mt2, &job.equal);
+  else
+    rc = pack_table<3>(sys, &job.mt3, &job.equal);
+  if (rc) return rc;
+  job.win = make_window(img, img->kind == CFS_IMAGE_U32_COUNT && img->channels > 1);
+  job.ra = make_run_args(run);
+  std::memcpy(job.fa.p, sys->final_params, sizeof job.fa.p);
+  job.img = img->data;
+  job.density = img->density;
+  job.near_plane = img->near_plane;
+  job.out.final_points = final_points;
+  job.out.last_index = last_index;
+  job.out.indices = indices;
+  job.out.dropped = img->dropped;
+  return device_status(launch_chaos(job, static_cast<hipStream_t>(stream)), "cfs_chaos_game");
+}
+
+extern "C" int cfs_philox_dump(uint64_t seed, const uint32_t *ctrs, uint32_t *out, uint64_t n,
+                               void *stream) {
+  clear_error();
+  if (n && (!ctrs || !out)) return fail(CFS_E_INVALID, "ctrs/out is NULL");
+  if (n > (1ull << 32)) return fail(CFS_E_INVALID, "n exceeds 2^32");
+  if ((reinterpret_cast<uintptr_t>(ctrs) | reinterpret_cast<uintptr_t>(out)) % 16)
+    return fail(CFS_E_INVALID, "ctrs/out must be 16-byte aligned");
+  return device_status(launch_philox_dump(static_cast<uint32_t>(seed),
+                                          static_cast<uint32_t>(seed >> 32), ctrs, out, n,
+                                          static_cast<hipStream_t>(stream)),
+                       "cfs_philox_dump");
+}

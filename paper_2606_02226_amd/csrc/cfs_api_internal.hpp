@@ -1,0 +1,22 @@
+// cfs_api_internal.hpp -- validation and packing helpers shared by the C-ABI
+// translation units of the library.
+#pragma once
+
+#include "cfs.h"
+#include "cfs_host.hpp"
+
+namespace cfs {
+
+int fail(int code, const char *fmt, ...);
+void clear_error();
+int device_status(hipError_t e, const char *what);
+int make_thresholds(const double *prob, int n, uint64_t *thresh);
+int validate_system(const cfs_system *s);
+int validate_run(const cfs_run *r);
+int validate_window(const cfs_image *img);
+Window make_window(const cfs_image *img, bool by_index);
+RunArgs make_run_args(const cfs_run *r);
+template <int DIM>
+int pack_table(const cfs_system *s, MapTable<DIM> *mt, bool *equal);
+
+}  // namespace cfs

@@ -1,0 +1,180 @@
+// cfs_device.hpp -- device building blocks of the chaos game on gfx950.
+//
+// One lane carries one point (Section 1 / Section 3 of the paper: every point
+// is independent; per-thread state is a handful of values).  The map table
+// lives in LDS and is gathered per lane by the drawn index, so there is no
+// per-lane branching on the index for affine maps; composed transforms are
+// compile-time kinds, so the whole wave takes the same path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cfs_params.hpp"
+
+namespace cfs {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Ten rounds; each
+// multiplies words 0 and 2 by the two round constants into 64-bit products
+// (one v_mad_u64_u32 each), xors the high halves with words 1/3 and the key,
+// and moves the low halves; the key advances by the Weyl constants.  The key
+// is wave-uniform, so its bumps stay on the scalar unit.
+// ---------------------------------------------------------------------------
+struct Block4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Block4 philox10(uint32_t x0, uint32_t x1, uint32_t x2,
+                                           uint32_t x3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t m0 = static_cast<uint64_t>(0xD2511F53u) * x0;
+    const uint64_t m1 = static_cast<uint64_t>(0xCD9E8D57u) * x2;
+    const uint32_t y0 = static_cast<uint32_t>(m1 >> 32) ^ x1 ^ k0;
+    const uint32_t y2 = static_cast<uint32_t>(m0 >> 32) ^ x3 ^ k1;
+    x1 = static_cast<uint32_t>(m1);
+    x3 = static_cast<uint32_t>(m0);
+    x0 = y0;
+    x2 = y2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Block4{x0, x1, x2, x3};
+}
+
+__device__ __forceinline__ uint32_t word_of(const Block4 &b, int j) {
+  return j == 0 ? b.w0 : (j == 1 ? b.w1 : (j == 2 ? b.w2 : b.w3));
+}
+
+// Initial point: tag 1, block 0; coordinate c = (word c >> 8) * 2^-24.
+template <typename real, int DIM>
+__device__ __forceinline__ void initial_point(uint32_t pid, uint32_t instance,
+                                              uint32_t k0, uint32_t k1, real p[DIM]) {
+  const Block4 w = philox10(pid, 0u, instance, 1u, k0, k1);
+  const real s = static_cast<real>(1.0 / 16777216.0);
+  p[0] = static_cast<real>(w.w0 >> 8) * s;
+  p[1] = static_cast<real>(w.w1 >> 8) * s;
+  if constexpr (DIM == 3) p[2] = static_cast<real>(w.w2 >> 8) * s;
+}
+
+// ---------------------------------------------------------------------------
+// Selection.  Equal probabilities: k = floor(u n / 2^32) (one mul_hi).
+// Otherwise a branch-free binary search for the number of thresholds <= u
+// among the n_search - 1 finite thresholds kept in LDS.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int select_equal(uint32_t u, uint32_t n) {
+  return static_cast<int>(__umulhi(u, n));
+}
+
+__device__ __forceinline__ int select_table(uint32_t u, const uint32_t *__restrict__ th,
+                                            int n_search, int top_step) {
+  int k = 0;
+  for (int step = top_step; step > 0; step >>= 1) {
+    const int probe = k + step;
+    if (probe <= n_search - 1 && th[probe - 1] <= u) k = probe;
+  }
+  return k;
+}
+
+// ---------------------------------------------------------------------------
+// Map table rows in LDS.  2D FP32 rows are 8 floats (two 16-byte reads);
+// 2D FP64 rows are 6 doubles; 3D rows hold A row-major then b.
+// ---------------------------------------------------------------------------
+template <typename real, int DIM>
+struct RowStride {
+  static constexpr int value = (DIM == 2) ? (sizeof(real) == 4 ? 8 : 6) : 12;
+};
+
+template <typename real, int DIM>
+__device__ __forceinline__ void apply_map(const real *__restrict__ table, int k, real p[DIM]) {
+  const real *r = table + k * RowStride<real, DIM>::value;
+  if constexpr (DIM == 2) {
+    const real x = p[0], y = p[1];
+    p[0] = r[0] * x + r[1] * y + r[4];
+    p[1] = r[2] * x + r[3] * y + r[5];
+  } else {
+    const real x = p[0], y = p[1], z = p[2];
+    p[0] = r[0] * x + r[1] * y + r[2] * z + r[9];
+    p[1] = r[3] * x + r[4] * y + r[5] * z + r[10];
+    p[2] = r[6] * x + r[7] * y + r[8] * z + r[11];
+  }
+}
+
+// Copy the kernel-argument map table into LDS rows of type `real`.
+template <typename real, int DIM>
+__device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
+                                           uint32_t *th) {
+  constexpr int S = RowStride<real, DIM>::value;
+  constexpr int C = DIM * (DIM + 1);
+  for (int i = threadIdx.x; i < mt.n_maps * S; i += blockDim.x) {
+    const int m = i / S, c = i % S;
+    real v = static_cast<real>(0);
+    if constexpr (DIM == 2) {
+      if (c < 6) v = static_cast<real>(mt.coef[m * C + c]);
+    } else {
+      v = static_cast<real>(mt.coef[m * C + c]);
+    }
+    table[i] = v;
+  }
+  for (int i = threadIdx.x; i < mt.n_search - 1; i += blockDim.x) th[i] = mt.thresh[i];
+}
+
+// ---------------------------------------------------------------------------
+// Composed transforms on the copy q of p (p is never modified).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sincos_r(float a, float *s, float *c) { sincosf(a, s, c); }
+__device__ __forceinline__ void sincos_r(double a, double *s, double *c) { sincos(a, s, c); }
+__device__ __forceinline__ float sqrt_r(float a) { return sqrtf(a); }
+__device__ __forceinline__ double sqrt_r(double a) { return sqrt(a); }
+__device__ __forceinline__ float cos_r(float a) { return cosf(a); }
+__device__ __forceinline__ double cos_r(double a) { return cos(a); }
+
+template <typename real, int FINAL, int DIM>
+__device__ __forceinline__ void final_transform(const float *__restrict__ fp, const real p[DIM],
+                                                real q[2], real *depth) {
+  if constexpr (FINAL == kFinalSwirl) {
+    const real cx = fp[0], cy = fp[1], kappa = fp[2], tx = fp[3], ty = fp[4];
+    const real dx = p[0] - cx, dy = p[1] - cy;
+    const real r = sqrt_r(dx * dx + dy * dy);
+    real s, c;
+    sincos_r(kappa * r, &s, &c);
+    q[0] = cx + tx + (c * dx - s * dy);
+    q[1] = cy + ty + (s * dx + c * dy);
+  } else if constexpr (FINAL == kFinalStretch) {
+    q[0] = static_cast<real>(fp[0]) * p[0];
+    q[1] = p[1] - static_cast<real>(fp[1]) * cos_r(p[0]);
+  } else if constexpr (FINAL == kFinalTwistCamera) {
+    const real wx = p[0] - static_cast<real>(fp[1]);
+    const real wy = p[1] - static_cast<real>(fp[2]);
+    const real wz = p[2] - static_cast<real>(fp[3]);
+    real s, c;
+    sincos_r(static_cast<real>(fp[0]) * wy, &s, &c);
+    const real tx = c * wx - s * wz;
+    const real tz = s * wx + c * wz;
+    const real vx = fp[4] * tx + fp[5] * wy + fp[6] * tz + fp[7];
+    const real vy = fp[8] * tx + fp[9] * wy + fp[10] * tz + fp[11];
+    const real vz = fp[12] * tx + fp[13] * wy + fp[14] * tz + fp[15];
+    q[0] = static_cast<real>(fp[16]) * vx / vz;
+    q[1] = static_cast<real>(fp[17]) * vy / vz;
+    *depth = vz;
+  } else {
+    q[0] = p[0];
+    q[1] = p[1];
+  }
+}
+
+// Pixel of q in the window, or -1 when it is dropped (outside or NaN).
+template <typename real>
+__device__ __forceinline__ int bin_pixel(const real q[2], const Window &w, int *ix_out) {
+  const real fx = (q[0] - static_cast<real>(w.lo[0])) * static_cast<real>(w.scale[0]);
+  const real fy = (q[1] - static_cast<real>(w.lo[1])) * static_cast<real>(w.scale[1]);
+  if (!(fx >= static_cast<real>(0) && fx < static_cast<real>(w.width))) return -1;
+  if (!(fy >= static_cast<real>(0) && fy < static_cast<real>(w.height))) return -1;
+  const int ix = static_cast<int>(fx);
+  const int iy = static_cast<int>(fy);
+  *ix_out = ix;
+  return iy * w.width + ix;
+}
+
+}  // namespace cfs

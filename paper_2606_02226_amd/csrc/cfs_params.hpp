@@ -1,0 +1,52 @@
+// cfs_params.hpp -- kernel-argument structs shared by the host launchers and
+// the kernels of the library (plain data, passed by value).
+#pragma once
+
+#include <stdint.h>
+
+namespace cfs {
+
+constexpr int kMaxMaps = 64;
+
+constexpr int kFinalIdentity = 0;
+constexpr int kFinalSwirl = 1;
+constexpr int kFinalTwistCamera = 2;
+constexpr int kFinalStretch = 3;
+
+// Map table of one system: per map A row-major then b (dim*(dim+1) floats),
+// and the finite selection thresholds.  n_search == 0 selects with equal
+// probabilities; otherwise thresh[0 .. n_search-2] are the thresholds that
+// are below 2^32 and the draw picks among the first n_search maps.
+template <int DIM>
+struct MapTable {
+  float coef[kMaxMaps * DIM * (DIM + 1)];
+  uint32_t thresh[kMaxMaps];
+  int32_t n_maps;
+  int32_t n_search;
+  int32_t top_step;  // largest power of two <= n_search - 1 (search start)
+};
+
+struct Window {
+  int32_t width, height, channels;
+  int32_t by_index;  // channel = last map index
+  double lo[2];
+  double scale[2];   // width / (hi - lo), height / (hi - lo)
+};
+
+struct RunArgs {
+  uint32_t k0, k1;   // Philox key (seed words)
+  uint32_t instance;
+  uint32_t n_points;
+  uint32_t point_offset;
+  uint32_t n_iters;
+  uint32_t burn_in;
+};
+
+struct Outputs {
+  void *final_points;          // float or double [N][dim], nullable
+  uint8_t *last_index;         // [N], nullable
+  uint8_t *indices;            // [N][T], nullable
+  unsigned long long *dropped; // nullable
+};
+
+}  // namespace cfs

@@ -1,0 +1,137 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/cfs.h declares, and rejects invalid arguments on the host before
+anything is enqueued.  Every invalid call below fails validation by
+construction (device pointers are NULL), so no kernel can be launched."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cfs.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_02226_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2606_02226_amd import build
+        build.build()
+    _lib.load()
+    return _lib
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cfs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_matches_binding_list(L):
+    assert header_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_header_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    defined = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [f for f in header_functions() if f not in defined]
+    assert not missing, missing
+
+
+def test_version(L):
+    assert L.load().cfs_version() == 1
+
+
+def _system(L, dim=2, n=3, A=None, b=None, prob=None, final_kind=0):
+    A = np.ascontiguousarray(A if A is not None else np.tile(np.eye(dim) * 0.5, (n, 1, 1)),
+                             np.float32)
+    b = np.ascontiguousarray(b if b is not None else np.zeros((n, dim)), np.float32)
+    keep = [A, b]
+    pp = None
+    if prob is not None:
+        prob = np.ascontiguousarray(prob, np.float64)
+        keep.append(prob)
+        pp = prob.ctypes.data_as(C.POINTER(C.c_double))
+    s = L.CfsSystem(dim, n, A.ctypes.data_as(C.POINTER(C.c_float)),
+                    b.ctypes.data_as(C.POINTER(C.c_float)), pp, final_kind,
+                    (C.c_float * 24)())
+    return s, keep
+
+
+def _run(L, n_points=10, n_iters=8, burn_in=2, precision=0, offset=0):
+    return L.CfsRun(0, 0, n_points, offset, n_iters, burn_in, precision)
+
+
+def _image(L, kind=0, W=16, H=16, ch=1, lo=(0, 0), hi=(1, 1)):
+    return L.CfsImage(kind, W, H, ch, (C.c_float * 2)(*lo), (C.c_float * 2)(*hi), 0.0,
+                      None, None, None)
+
+
+def _call(L, s, r, img):
+    lib = L.load()
+    return lib.cfs_chaos_game(C.byref(s), C.byref(r), C.byref(img), None, None, None, None,
+                              0, None)
+
+
+CASES = [
+    ("dim", dict(sys=dict(dim=4)), "dim must be 2 or 3"),
+    ("n_maps0", dict(sys=dict(n=0)), "n_maps must be"),
+    ("n_maps65", dict(sys=dict(n=65)), "n_maps must be"),
+    ("nanA", dict(sys=dict(A=np.full((3, 2, 2), np.nan))), "A[0] is not finite"),
+    ("infb", dict(sys=dict(b=np.full((3, 2), np.inf))), "b[0] is not finite"),
+    ("final", dict(sys=dict(final_kind=9)), "unknown final kind"),
+    ("swirl3d", dict(sys=dict(dim=3, final_kind=1)), "needs dim 2"),
+    ("camera2d", dict(sys=dict(final_kind=2)), "needs dim 3"),
+    ("iters0", dict(run=dict(n_iters=0)), "n_iters must be"),
+    ("burn", dict(run=dict(burn_in=9)), "burn_in"),
+    ("offset", dict(run=dict(offset=2**32 - 5)), "exceeds 2^32"),
+    ("prec", dict(run=dict(precision=7)), "precision"),
+    ("width", dict(img=dict(W=0)), "image size"),
+    ("height", dict(img=dict(H=70000)), "image size"),
+    ("window", dict(img=dict(lo=(1, 0), hi=(1, 1))), "lo < hi"),
+    ("data", dict(), "image data is NULL"),
+]
+
+
+@pytest.mark.parametrize("name,kw,msg", CASES, ids=[c[0] for c in CASES])
+def test_invalid_arguments(L, name, kw, msg):
+    sk = dict(kw.get("sys", {}))
+    dim = sk.get("dim", 2)
+    n = sk.get("n", 3)
+    if dim == 4 or n in (0, 65):
+        sk.setdefault("A", np.zeros((max(n, 1), 2, 2)))
+        sk.setdefault("b", np.zeros((max(n, 1), 2)))
+        s, keep = _system(L, dim=2, n=max(n, 1), A=sk["A"], b=sk["b"])
+        s.dim, s.n_maps = dim, n
+    else:
+        s, keep = _system(L, **sk)
+    r = _run(L, **kw.get("run", {}))
+    img = _image(L, **kw.get("img", {}))
+    rc = _call(L, s, r, img)
+    assert rc == L.CFS_E_INVALID
+    assert msg in L.load().cfs_last_error().decode()
+
+
+def test_bad_probabilities(L):
+    s, keep = _system(L, prob=[0.5, 0.6, 0.1])
+    rc = _call(L, s, _run(L), _image(L))
+    assert rc == L.CFS_E_INVALID
+    assert "sum to" in L.load().cfs_last_error().decode()
+    s, keep = _system(L, prob=[0.5, -0.1, 0.6])
+    assert _call(L, s, _run(L), _image(L)) == L.CFS_E_INVALID
+
+
+def test_null_structs(L):
+    lib = L.load()
+    assert lib.cfs_chaos_game(None, None, None, None, None, None, None, 0, None) == L.CFS_E_INVALID
+    assert "NULL" in lib.cfs_last_error().decode()
+    assert lib.cfs_image_clear(None, None) == L.CFS_E_INVALID
+
+
+def test_philox_dump_rejects_null(L):
+    lib = L.load()
+    assert lib.cfs_philox_dump(0, None, None, 4, None) == L.CFS_E_INVALID

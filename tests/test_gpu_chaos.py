@@ -1,0 +1,239 @@
+"""GPU parity of the plain chaos game (cfs_chaos_game, cfs_philox_dump,
+cfs_image_clear) against the FP64 oracle, through the C ABI.
+
+Bars: Philox blocks and index sequences bit-exact; final positions within
+1e-5 absolute; integer histograms within 1e-4 relative L1 of the total and
+inside the guard-band interval [sure, sure + maybe] built from the oracle's
+FP64 splat coordinates; totals exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import guard_band_images, guard_band_violations, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_02226_amd import api as _api
+    return _api
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def run_gpu(api, w, precision="f32", want_indices=False, want_final=True, system=None,
+            run=None, image=None):
+    system = system or w["system"]
+    run = run or w["run"]
+    image_desc = image or w["image"]
+    N, T, d = run["n_points"], run["n_iters"], system["dim"]
+    img = api.Image(image_desc, device=_dev()).clear()
+    ftype = torch.float32 if precision == "f32" else torch.float64
+    fin = torch.empty((N, d), dtype=ftype, device=_dev()) if want_final else None
+    last = torch.empty((N,), dtype=torch.uint8, device=_dev())
+    idx = torch.empty((N, T), dtype=torch.uint8, device=_dev()) if want_indices else None
+    api.chaos_game(system, run, img, precision=precision, final=fin, last=last, indices=idx)
+    out = img.to_numpy()
+    out["final"] = None if fin is None else fin.cpu().numpy().astype(np.float64)
+    out["last"] = last.cpu().numpy()
+    out["indices"] = None if idx is None else idx.cpu().numpy()
+    return out
+
+
+def test_philox_dump_bitexact(api, orc):
+    rng = np.random.default_rng(1)
+    ctrs = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctrs[0] = 0
+    ctrs[1] = 0xFFFFFFFF
+    for seed in (0, 0xFFFFFFFFFFFFFFFF, 0x0123456789ABCDEF):
+        dev = torch.from_numpy(ctrs.view(np.int32)).to(_dev())
+        got = api.philox_dump(seed, dev).cpu().numpy().view(np.uint32)
+        ref = orc.philox_many(seed, ctrs)
+        assert np.array_equal(got, ref)
+
+
+def test_sierpinski_full_parity(api, orc):
+    """Sierpinski: 2^16 points x 64 iterations (16 burn-in), FP32 points,
+    512x512 u32 over [0,1]^2 -- the full configuration."""
+    w = W.sierpinski()
+    N, T, B = 1 << 16, 64, 16
+    got = run_gpu(api, w, "f32", want_indices=True)
+    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True,
+                          want_last=True, want_indices=True, want_splats=True)
+    assert np.array_equal(got["indices"], ref["indices"])
+    assert np.array_equal(got["last"], ref["last"])
+    err = np.max(np.abs(got["final"] - ref["final"]))
+    assert err <= 1e-5, err
+    h, r = got["image"], ref["image"]
+    assert int(h.astype(np.int64).sum()) == N * (T - B) == int(r.astype(np.int64).sum())
+    assert got["dropped"] == 0
+    l1 = rel_l1(h, r)
+    print(f"sierpinski f32: max|dp|={err:.3e} relL1={l1:.3e}")
+    assert l1 <= 1e-4, l1
+    sure, maybe = guard_band_images(ref["splats"], 0, 512, 512, 1, eps_px=512 * 2e-6)
+    assert guard_band_violations(h, sure, maybe) == (0, 0)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_cfs_square_parity(api, orc, precision):
+    """CFS square + swirl + translation, 4 channels by last index, full
+    2048x2048 image, 2^16 points (the oracle's share of the full run)."""
+    w = W.cfs_square(n_points=1 << 16)
+    N, T, B = 1 << 16, 32, 8
+    got = run_gpu(api, w, precision, want_indices=True)
+    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True,
+                          want_last=True, want_indices=True, want_splats=True)
+    assert np.array_equal(got["indices"], ref["indices"])
+    assert np.array_equal(got["last"], ref["last"])
+    err = np.max(np.abs(got["final"] - ref["final"]))
+    assert err <= 1e-5, err
+    h, r = got["image"], ref["image"]
+    assert got["dropped"] == 0 and int(h.astype(np.int64).sum()) == N * (T - B)
+    # per-channel totals depend only on the (bit-exact) indices
+    assert np.array_equal(h.astype(np.int64).sum(axis=(1, 2)), r.astype(np.int64).sum(axis=(1, 2)))
+    l1 = rel_l1(h, r)
+    eps = 1024 * (1e-12 if precision == "f64" else 2e-6)
+    chan = ref["indices"][:, B:]
+    sure, maybe = guard_band_images(ref["splats"], chan, 2048, 2048, 4, eps_px=eps)
+    viol = guard_band_violations(h, sure, maybe)
+    print(f"cfs_square {precision}: max|dp|={err:.3e} relL1={l1:.3e} guard={viol}")
+    assert viol == (0, 0)
+    if precision == "f64":
+        assert l1 <= 1e-4, l1
+
+
+def test_point_range_split_bitexact(api):
+    w = W.cfs_square(n_points=5000, side=512)
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(w["system"], w["run"], img, precision="f64")
+    whole = img.to_numpy()["image"].copy()
+    img.clear()
+    api.chaos_game(w["system"], dict(w["run"], n_points=1234), img, precision="f64")
+    api.chaos_game(w["system"], dict(w["run"], n_points=5000 - 1234, point_offset=1234), img,
+                   precision="f64")
+    assert np.array_equal(img.to_numpy()["image"], whole)
+
+
+def test_run_to_run_bitexact(api):
+    w = W.cfs_square(n_points=1 << 18)
+    a = run_gpu(api, w, "f32", want_final=False)["image"]
+    b = run_gpu(api, w, "f32", want_final=False)["image"]
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n_points,n_iters,burn_in", [
+    (1, 1, 0), (1, 7, 7), (255, 5, 2), (257, 13, 3), (1000, 64, 63), (4099, 9, 0)])
+def test_ragged_shapes(api, orc, n_points, n_iters, burn_in):
+    w = W.sierpinski(n_points=n_points, n_iters=n_iters, burn_in=burn_in, side=64)
+    got = run_gpu(api, w, "f64", want_indices=True)
+    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True,
+                          want_last=True, want_indices=True)
+    assert np.array_equal(got["indices"], ref["indices"])
+    assert np.array_equal(got["last"], ref["last"])
+    assert np.max(np.abs(got["final"] - ref["final"])) <= 1e-12
+    assert np.array_equal(got["image"], ref["image"])
+
+
+def test_zero_points_is_noop(api):
+    w = W.sierpinski(n_points=0, side=32)
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(w["system"], w["run"], img)
+    assert int(img.to_numpy()["image"].astype(np.int64).sum()) == 0
+
+
+def test_unequal_probabilities_and_dead_maps(api, orc):
+    # 16 maps: zero-probability maps are never drawn; a prefix that already
+    # sums to one leaves every later map unreachable
+    rng = np.random.default_rng(9)
+    n = 16
+    A = np.stack([np.eye(2) * 0.4] * n).astype(np.float32)
+    b = rng.uniform(0, 0.6, size=(n, 2)).astype(np.float32)
+    p_dead = rng.dirichlet(np.ones(n))
+    p_dead[[3, 15]] = 0.0
+    p_dead /= p_dead.sum()
+    p_prefix = np.zeros(n)
+    p_prefix[:2] = 0.5
+    for prob in (p_dead, p_prefix, rng.dirichlet(np.ones(n))):
+        system = W._system(A, b, prob=prob)
+        run = {"seed": 7, "instance": 3, "n_points": 3000, "point_offset": 11,
+               "n_iters": 20, "burn_in": 4}
+        img = {"kind": "u32_count", "width": 128, "height": 128, "channels": 1,
+               "lo": [0, 0], "hi": [1, 1]}
+        got = run_gpu(api, None, "f64", want_indices=True, system=system, run=run, image=img)
+        ref = orc.chaos_count(system, run, img, want_last=True, want_indices=True)
+        assert np.array_equal(got["indices"], ref["indices"])
+        counts = np.bincount(ref["indices"].reshape(-1), minlength=n)
+        assert np.all(counts[prob == 0] == 0)
+        assert np.array_equal(got["image"], ref["image"])
+
+
+def test_3d_identity_counts(api, orc):
+    w = W.menger(n_points=4096, side=64)
+    system = dict(w["system"], final_kind="identity")
+    img = {"kind": "u32_count", "width": 81, "height": 81, "channels": 1,
+           "lo": [0, 0], "hi": [1, 1]}
+    got = run_gpu(api, w, "f64", want_indices=True, system=system, image=img)
+    ref = orc.chaos_count(system, w["run"], img, want_final=True, want_indices=True)
+    assert np.array_equal(got["indices"], ref["indices"])
+    assert np.max(np.abs(got["final"] - ref["final"])) <= 1e-12
+    assert rel_l1(got["image"], ref["image"]) <= 1e-4
+
+
+def test_stretch_transform(api, orc):
+    w = W.cfs_square(n_points=4096, side=256)
+    system = dict(w["system"], final_kind="stretch",
+                  final_params=np.array([2.0, 1.0] + [0.0] * 22, np.float32))
+    img = {"kind": "u32_count", "width": 256, "height": 256, "channels": 4,
+           "lo": [0.0, -1.0], "hi": [2.0, 1.0]}
+    got = run_gpu(api, w, "f64", system=system, image=img)
+    ref = orc.chaos_count(system, w["run"], img)
+    assert rel_l1(got["image"], ref["image"]) <= 1e-4
+    assert got["dropped"] == ref["dropped"]
+
+
+def test_menger_depth_parity(api, orc):
+    w = W.menger(n_points=1 << 14, side=1024)
+    got_img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(w["system"], w["run"], got_img, precision="f64")
+    got = got_img.to_numpy()
+    ref = orc.chaos_depth(w["system"], w["run"], w["image"], w["image"]["near"])
+    assert got["dropped"] == ref["dropped"]
+    assert rel_l1(got["density"], ref["density"]) <= 1e-4
+    same = np.mean(got["depth"] == ref["depth"])
+    print(f"menger f64: density relL1={rel_l1(got['density'], ref['density']):.2e} depth equal={same:.6f}")
+    assert same >= 1 - 1e-4
+
+
+def test_image_clear(api):
+    desc = {"kind": "u64_depth", "width": 37, "height": 5, "channels": 1,
+            "lo": [-1, -1], "hi": [1, 1], "near": 0.1}
+    img = api.Image(desc, device=_dev())
+    img.data.fill_(5)
+    img.density.fill_(7)
+    img.dropped.fill_(3)
+    img.clear()
+    out = img.to_numpy()
+    assert np.all(out["depth"] == np.iinfo(np.uint64).max)
+    assert np.all(out["density"] == 0) and out["dropped"] == 0
+    # odd offsets exercise the unaligned head of the 16-byte clear
+    base = torch.full((1001,), 9, dtype=torch.int32, device=_dev())
+    for off in (0, 1, 2, 3):
+        view = base[off:off + 997]
+        d = {"kind": "u32_count", "width": 997, "height": 1, "channels": 1,
+             "lo": [0, 0], "hi": [1, 1]}
+        im = api.Image(d, device=_dev(), data=view)
+        base.fill_(9)
+        im.clear()
+        host = base.cpu().numpy()
+        assert np.all(host[off:off + 997] == 0)
+        assert np.all(host[:off] == 9) and np.all(host[off + 997:] == 9)
