@@ -94,6 +94,14 @@ enum {
 /* Arithmetic type of the point positions and transforms on the GPU. */
 enum { CFS_PREC_F32 = 0, CFS_PREC_F64 = 1 };
 
+/* How integer count splats reach the image.  DIRECT: one device atomic per
+ * splat.  BINNED: each workgroup sorts its splats by image tile in LDS and
+ * writes them out as per-tile runs; a second kernel accumulates every tile
+ * in LDS and adds it into the image (needs workspace, images of at most
+ * 2^26 elements).  AUTO picks BINNED for large runs that qualify.  Both give
+ * bit-identical images. */
+enum { CFS_SPLAT_AUTO = 0, CFS_SPLAT_DIRECT = 1, CFS_SPLAT_BINNED = 2 };
+
 /* A function system: n affine maps p -> A_k p + b_k and a composed transform.
  * The map table is copied into kernel arguments (a few KiB at most). */
 typedef struct cfs_system {
@@ -115,6 +123,7 @@ typedef struct cfs_run {
   uint32_t n_iters;       /* T map applications per point, 1 .. 2^20 */
   uint32_t burn_in;       /* B <= T: iterations 1..B are not splatted */
   int32_t precision;      /* CFS_PREC_F32 or CFS_PREC_F64 */
+  int32_t splat_path;     /* CFS_SPLAT_AUTO / _DIRECT / _BINNED (count images) */
 } cfs_run;
 
 /* An output image in device memory. */

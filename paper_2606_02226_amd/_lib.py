@@ -22,6 +22,7 @@ CFS_MAX_MAPS = 64
 FINAL_KINDS = {"identity": 0, "swirl": 1, "twist_camera": 2, "stretch": 3}
 IMAGE_KINDS = {"u32_count": 0, "f32_density": 1, "u64_depth": 2}
 PRECISIONS = {"f32": 0, "f64": 1}
+SPLAT_PATHS = {"auto": 0, "direct": 1, "binned": 2}
 
 # Every symbol include/cfs.h declares.
 EXPORTS = (
@@ -43,7 +44,7 @@ class CfsRun(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32),
                 ("n_points", C.c_uint32), ("point_offset", C.c_uint32),
                 ("n_iters", C.c_uint32), ("burn_in", C.c_uint32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("splat_path", C.c_int32)]
 
 
 class CfsImage(C.Structure):

@@ -52,11 +52,11 @@ class System:
         self.dim, self.n_maps = d, n
 
 
-def run_struct(run, precision="f32"):
+def run_struct(run, precision="f32", splat_path="auto"):
     return CfsRun(int(run.get("seed", 0)), int(run.get("instance", 0)),
                   int(run["n_points"]), int(run.get("point_offset", 0)),
                   int(run["n_iters"]), int(run["burn_in"]),
-                  _lib.PRECISIONS[precision])
+                  _lib.PRECISIONS[precision], _lib.SPLAT_PATHS[splat_path])
 
 
 class Image:
@@ -118,8 +118,12 @@ def image_clear(image, stream=None):
 
 
 def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
-               indices=None, stream=None):
+               indices=None, splat_path="auto", workspace=None, stream=None):
     """Enqueue the plain chaos game (cfs_chaos_game) into ``image``.
+
+    ``splat_path`` is 'auto', 'direct' or 'binned'; ``workspace`` is an
+    optional uint8 device tensor reused across calls (allocated here when
+    missing or too small).
 
     ``system`` is a workload system dict or a :class:`System`; ``final``
     (float32/float64 [N][dim]), ``last`` (uint8 [N]) and ``indices``
@@ -127,17 +131,28 @@ def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
     """
     lib = _lib.load()
     sysc = system if isinstance(system, System) else System(system)
-    runc = run_struct(run, precision)
+    runc = run_struct(run, precision, splat_path)
     ws_bytes = lib.cfs_chaos_game_workspace(C.byref(sysc.struct), C.byref(runc),
                                             C.byref(image.struct))
     ws = None
     if ws_bytes:
-        ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device=image.data.device)
+        if workspace is not None and workspace.numel() >= ws_bytes:
+            ws = workspace
+        else:
+            ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device=image.data.device)
     rc = lib.cfs_chaos_game(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
                             _ptr(final), _ptr(last), _ptr(indices), _ptr(ws),
                             C.c_size_t(ws_bytes), _stream_handle(stream))
     check(rc, "cfs_chaos_game")
     return image
+
+
+def chaos_workspace_bytes(system, run, image, precision="f32", splat_path="auto"):
+    lib = _lib.load()
+    sysc = system if isinstance(system, System) else System(system)
+    runc = run_struct(run, precision, splat_path)
+    return int(lib.cfs_chaos_game_workspace(C.byref(sysc.struct), C.byref(runc),
+                                            C.byref(image.struct)))
 
 
 def philox_dump(seed, ctrs, stream=None):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -225,12 +226,46 @@ extern "C" int cfs_image_clear(const cfs_image *img, void *stream) {
   return device_status(e, "cfs_image_clear");
 }
 
+namespace {
+
+// Points per launch of the binned path: at most 2^24, and few enough that the
+// records of one launch take at most 1 GiB (2^29 16-bit records), which also
+// keeps record indices within 31 bits.
+uint32_t binned_slice(const cfs_run *run) {
+  const uint64_t flushes = (run->n_iters - run->burn_in + kBinSlots - 1) / kBinSlots;
+  uint64_t max_blocks = (1ull << 29) / (flushes * kChunkCap);
+  if (max_blocks < 1) max_blocks = 1;
+  uint64_t pts = max_blocks * kBinBlock;
+  if (pts > (1ull << 24)) pts = 1ull << 24;
+  if (pts > run->n_points) pts = run->n_points;
+  return static_cast<uint32_t>(pts);
+}
+
+// Whether this call takes the binned splat (arguments already validated).
+bool use_binned(const cfs_run *run, const cfs_image *img) {
+  if (img->kind != CFS_IMAGE_U32_COUNT || run->splat_path == CFS_SPLAT_DIRECT) return false;
+  if (run->n_iters == run->burn_in || run->n_points == 0) return false;
+  const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
+  if (elems > static_cast<uint64_t>(kMaxTiles) * kTileElems) return false;
+  if (run->splat_path == CFS_SPLAT_BINNED) return true;
+  return static_cast<uint64_t>(run->n_points) * (run->n_iters - run->burn_in) >= (1ull << 20);
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+size_t binned_workspace(const cfs_run *run, const cfs_image *img) {
+  const uint32_t elems = static_cast<uint32_t>(img->width) * img->height * img->channels;
+  const BinPlan bp = bin_plan(binned_slice(run), run->n_iters, run->burn_in, elems);
+  return align_up(bp.records_bytes) + align_up(bp.table_bytes);
+}
+
+}  // namespace
+
 extern "C" size_t cfs_chaos_game_workspace(const cfs_system *sys, const cfs_run *run,
                                            const cfs_image *img) {
-  (void)sys;
-  (void)run;
-  (void)img;
-  return 0;
+  if (validate_system(sys) || validate_run(run) || validate_window(img)) return 0;
+  if (!use_binned(run, img)) return 0;
+  return binned_workspace(run, img);
 }
 
 extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
@@ -241,8 +276,8 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
   if (!rc) rc = validate_run(run);
   if (!rc) rc = validate_window(img);
   if (rc) return rc;
-  (void)workspace;
-  (void)workspace_bytes;
+  if (run->splat_path < CFS_SPLAT_AUTO || run->splat_path > CFS_SPLAT_BINNED)
+    return fail(CFS_E_INVALID, "unknown splat_path %d", run->splat_path);
   ChaosJob job;
   std::memset(&job, 0, sizeof job);
   job.dim = sys->dim;
@@ -260,13 +295,28 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
       return fail(CFS_E_UNSUPPORTED, "a depth image needs the twist/camera transform");
     if (!std::isfinite(img->near_plane))
       return fail(CFS_E_INVALID, "near_plane is not finite");
+    if (run->splat_path == CFS_SPLAT_BINNED)
+      return fail(CFS_E_UNSUPPORTED, "depth images take the direct splat");
     job.depth = true;
   } else {
     return fail(CFS_E_INVALID, "cfs_chaos_game renders U32_COUNT or U64_DEPTH images");
   }
+  const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
+  if (run->splat_path == CFS_SPLAT_BINNED && elems > static_cast<uint64_t>(kMaxTiles) * kTileElems)
+    return fail(CFS_E_UNSUPPORTED, "binned splat handles images of at most 2^26 elements");
   const size_t align = run->precision == CFS_PREC_F64 ? 8 : 4;
   if (final_points && reinterpret_cast<uintptr_t>(final_points) % align)
     return fail(CFS_E_INVALID, "final_points is not %zu-byte aligned", align);
+  job.binned = use_binned(run, img);
+  size_t need = 0;
+  if (job.binned) {
+    need = binned_workspace(run, img);
+    if (!workspace || workspace_bytes < need)
+      return fail(CFS_E_WORKSPACE, "binned splat needs %zu bytes of workspace, got %zu", need,
+                  workspace ? workspace_bytes : static_cast<size_t>(0));
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+      return fail(CFS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  }
   if (sys->dim == 2)
     rc = pack_table<2>(sys, &job.mt2, &job.equal);
   else
@@ -282,7 +332,32 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
   job.out.last_index = last_index;
   job.out.indices = indices;
   job.out.dropped = img->dropped;
-  return device_status(launch_chaos(job, static_cast<hipStream_t>(stream)), "cfs_chaos_game");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!job.binned) return device_status(launch_chaos(job, s), "cfs_chaos_game");
+
+  // binned: slices of at most binned_slice() points share the workspace
+  const uint32_t slice = binned_slice(run);
+  const size_t real_bytes = run->precision == CFS_PREC_F64 ? sizeof(double) : sizeof(float);
+  for (uint32_t done = 0; done < run->n_points; done += slice) {
+    const uint32_t pts = std::min(slice, run->n_points - done);
+    const BinPlan bp = bin_plan(pts, run->n_iters, run->burn_in, static_cast<uint32_t>(elems));
+    ChaosJob sj = job;
+    sj.ra.n_points = pts;
+    sj.ra.point_offset = run->point_offset + done;
+    if (final_points)
+      sj.out.final_points = static_cast<char *>(final_points) + static_cast<size_t>(done) * sys->dim * real_bytes;
+    if (last_index) sj.out.last_index = last_index + done;
+    if (indices) sj.out.indices = indices + static_cast<size_t>(done) * run->n_iters;
+    sj.ba.records = static_cast<uint16_t *>(workspace);
+    sj.ba.tile_start = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + align_up(bp.records_bytes));
+    sj.ba.n_chunks = bp.n_chunks;
+    sj.ba.flushes = bp.flushes;
+    sj.ba.n_tiles = bp.n_tiles;
+    sj.ba.elems = bp.elems;
+    rc = device_status(launch_chaos_binned(sj, s), "cfs_chaos_game");
+    if (rc) return rc;
+  }
+  return CFS_OK;
 }
 
 extern "C" int cfs_philox_dump(uint64_t seed, const uint32_t *ctrs, uint32_t *out, uint64_t n,

@@ -18,6 +18,7 @@ struct ChaosJob {
   int precision;  // 0 = FP32, 1 = FP64
   bool equal;     // equal probabilities
   bool depth;     // U64 depth image (3D camera)
+  bool binned;    // binned count splat (needs ba)
   MapTable<2> mt2;
   MapTable<3> mt3;
   Window win;
@@ -27,7 +28,17 @@ struct ChaosJob {
   uint32_t *density;
   float near_plane;
   Outputs out;
+  BinArgs ba;
 };
+
+// Records and table sizes of the binned splat for one launch of `points`.
+struct BinPlan {
+  uint32_t blocks, flushes, n_chunks, n_tiles, elems;
+  size_t records_bytes, table_bytes;
+};
+BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems);
+
+hipError_t launch_chaos_binned(const ChaosJob &job, hipStream_t stream);
 
 hipError_t launch_chaos(const ChaosJob &job, hipStream_t stream);
 hipError_t launch_clear_u32(uint32_t *p, size_t n, hipStream_t stream);

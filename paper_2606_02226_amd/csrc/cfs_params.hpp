@@ -42,6 +42,27 @@ struct RunArgs {
   uint32_t burn_in;
 };
 
+// Binned integer splat: a workgroup of kBinBlock lanes collects kBinSlots
+// splats per lane (one chunk of kChunkCap records), sorts them by image tile
+// of kTileElems elements in LDS and writes each tile's records as a run of
+// 16-bit in-tile offsets; a per-tile kernel then accumulates the runs in LDS.
+constexpr int kBinBlock = 1024;
+constexpr int kBinSlots = 24;
+constexpr uint32_t kChunkCap = static_cast<uint32_t>(kBinBlock) * kBinSlots;
+constexpr int kTileBits = 15;
+constexpr uint32_t kTileElems = 1u << kTileBits;
+constexpr int kMaxTiles = 2048;
+constexpr int kAccBlock = 1024;
+
+struct BinArgs {
+  uint16_t *records;     // [n_chunks][kChunkCap] in-tile offsets, runs by tile
+  uint32_t *tile_start;  // [n_tiles + 1][n_chunks]: absolute record index
+  uint32_t n_chunks;     // chunks of this launch (= blocks * flushes)
+  uint32_t flushes;      // chunks per workgroup
+  uint32_t n_tiles;
+  uint32_t elems;        // image elements (channels * height * width)
+};
+
 struct Outputs {
   void *final_points;          // float or double [N][dim], nullable
   uint8_t *last_index;         // [N], nullable

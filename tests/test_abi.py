@@ -63,7 +63,7 @@ def _system(L, dim=2, n=3, A=None, b=None, prob=None, final_kind=0):
 
 
 def _run(L, n_points=10, n_iters=8, burn_in=2, precision=0, offset=0):
-    return L.CfsRun(0, 0, n_points, offset, n_iters, burn_in, precision)
+    return L.CfsRun(0, 0, n_points, offset, n_iters, burn_in, precision, 0)
 
 
 def _image(L, kind=0, W=16, H=16, ch=1, lo=(0, 0), hi=(1, 1)):

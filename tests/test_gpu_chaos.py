@@ -237,3 +237,120 @@ def test_image_clear(api):
         host = base.cpu().numpy()
         assert np.all(host[off:off + 997] == 0)
         assert np.all(host[:off] == 9) and np.all(host[off + 997:] == 9)
+
+
+# ---------------------------------------------------------------------------
+# Binned splat: bit-identical to the direct splat, same parity bars
+# ---------------------------------------------------------------------------
+def _image_of(api, w, precision, splat_path, system=None, run=None, image=None):
+    img = api.Image(image or w["image"], device=_dev()).clear()
+    api.chaos_game(system or w["system"], run or w["run"], img, precision=precision,
+                   splat_path=splat_path)
+    return img.to_numpy()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_binned_equals_direct_square(api, precision):
+    w = W.cfs_square(n_points=(1 << 18) + 77)
+    a = _image_of(api, w, precision, "direct")
+    b = _image_of(api, w, precision, "binned")
+    assert np.array_equal(a["image"], b["image"]) and a["dropped"] == b["dropped"] == 0
+
+
+def test_binned_sierpinski_parity(api, orc):
+    w = W.sierpinski()
+    got = _image_of(api, w, "f32", "binned")
+    ref = orc.chaos_count(w["system"], w["run"], w["image"])
+    assert int(got["image"].astype(np.int64).sum()) == (1 << 16) * 48
+    assert rel_l1(got["image"], ref["image"]) <= 1e-4
+    assert np.array_equal(got["image"], _image_of(api, w, "f32", "direct")["image"])
+
+
+def test_binned_drops_and_ragged(api, orc):
+    # window cut through the attractor: splats outside are dropped and counted;
+    # a ragged image (not a multiple of the tile) and ragged point count
+    w = W.sierpinski(n_points=5000, n_iters=37, burn_in=5)
+    image = {"kind": "u32_count", "width": 333, "height": 211, "channels": 1,
+             "lo": [0.2, 0.1], "hi": [0.9, 0.7]}
+    got = _image_of(api, w, "f64", "binned", image=image)
+    ref = orc.chaos_count(w["system"], w["run"], image)
+    assert np.array_equal(got["image"], ref["image"])
+    assert got["dropped"] == ref["dropped"] > 0
+
+
+def test_binned_slices_long_runs(api):
+    # 1000 splats per point: the run is split into several slices that share
+    # the workspace; the image must equal the direct splat's
+    w = W.cfs_square(n_points=(1 << 22) + 5, n_iters=1004, burn_in=4, side=1024)
+    sysw = dict(w["system"], final_kind="identity")
+    image = dict(w["image"], lo=[0, 0], hi=[1, 1])
+    img = api.Image(image, device=_dev())
+    nbytes = api.chaos_workspace_bytes(sysw, w["run"], img, "f32", "binned")
+    assert 0 < nbytes < (1 << 32)
+    a = _image_of(api, w, "f32", "direct", system=sysw, image=image)
+    b = _image_of(api, w, "f32", "binned", system=sysw, image=image)
+    assert np.array_equal(a["image"], b["image"]) and a["dropped"] == b["dropped"]
+    # FP32 can round x/2 + 1/2 up to exactly 1.0 (a tie from 1 - 2^-24), which is
+    # outside the half-open window: such splats are dropped and counted
+    assert int(b["image"].astype(np.int64).sum()) + b["dropped"] == ((1 << 22) + 5) * 1000
+
+
+def test_binned_unequal_probabilities_3d(api, orc):
+    w = W.menger(n_points=20000, side=64)
+    rng = np.random.default_rng(2)
+    prob = rng.dirichlet(np.ones(20))
+    system = dict(w["system"], final_kind="identity", prob=prob)
+    image = {"kind": "u32_count", "width": 300, "height": 300, "channels": 20,
+             "lo": [0, 0], "hi": [1, 1]}
+    got = _image_of(api, w, "f64", "binned", system=system, image=image)
+    ref = orc.chaos_count(system, w["run"], image)
+    assert np.array_equal(got["image"], ref["image"])
+
+
+def test_binned_workspace_too_small(api):
+    from paper_2606_02226_amd import _lib
+    import ctypes as C
+    w = W.cfs_square(n_points=1 << 16)
+    img = api.Image(w["image"], device=_dev()).clear()
+    sysc = api.System(w["system"])
+    runc = api.run_struct(w["run"], "f64", "binned")
+    need = _lib.load().cfs_chaos_game_workspace(C.byref(sysc.struct), C.byref(runc),
+                                                C.byref(img.struct))
+    small = torch.empty(int(need) // 2, dtype=torch.uint8, device=_dev())
+    rc = _lib.load().cfs_chaos_game(C.byref(sysc.struct), C.byref(runc), C.byref(img.struct),
+                                    None, None, None, C.c_void_p(small.data_ptr()),
+                                    C.c_size_t(small.numel()), None)
+    assert rc == _lib.CFS_E_WORKSPACE
+    assert int(img.to_numpy()["image"].astype(np.int64).sum()) == 0
+
+
+def test_full_size_cfs_square_sampled(api, orc):
+    """The benchmark configuration (2^24 points, FP64, binned) checked on
+    sampled points computed one by one by the oracle, on exact totals and
+    against the direct splat bit for bit."""
+    w = W.cfs_square()
+    N, T, B = 1 << 24, 32, 8
+    img = api.Image(w["image"], device=_dev()).clear()
+    fin = torch.empty((N, 2), dtype=torch.float64, device=_dev())
+    last = torch.empty((N,), dtype=torch.uint8, device=_dev())
+    api.chaos_game(w["system"], w["run"], img, precision="f64", final=fin, last=last,
+                   splat_path="binned")
+    got = img.to_numpy()
+    h = got["image"].astype(np.int64)
+    assert got["dropped"] == 0 and int(h.sum()) == N * (T - B)
+    tot = h.sum(axis=(1, 2))
+    # per-channel totals: binomial(N (T-B), 1/4) within 6 sigma
+    sd = math.sqrt(N * (T - B) * 0.25 * 0.75)
+    assert np.all(np.abs(tot - N * (T - B) / 4) < 6 * sd)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(N, size=512, replace=False))
+    sample[0], sample[-1] = 0, N - 1
+    fs = fin[torch.from_numpy(sample).to(_dev())].cpu().numpy()
+    ls = last[torch.from_numpy(sample).to(_dev())].cpu().numpy()
+    for i, pid in enumerate(sample):
+        r = orc.chaos_count(w["system"], dict(w["run"], n_points=1, point_offset=int(pid)),
+                            w["image"], want_final=True, want_last=True)
+        assert r["last"][0] == ls[i]
+        assert np.max(np.abs(r["final"][0] - fs[i])) <= 1e-12
+    direct = _image_of(api, w, "f64", "direct")
+    assert np.array_equal(direct["image"], got["image"])
