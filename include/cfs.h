@@ -98,7 +98,7 @@ enum { CFS_PREC_F32 = 0, CFS_PREC_F64 = 1 };
  * splat.  BINNED: each workgroup sorts its splats by image tile in LDS and
  * writes them out as per-tile runs; a second kernel accumulates every tile
  * in LDS and adds it into the image (needs workspace, images of at most
- * 2^26 elements).  AUTO picks BINNED for large runs that qualify.  Both give
+ * 2^25 elements).  AUTO picks BINNED for large runs that qualify.  Both give
  * bit-identical images. */
 enum { CFS_SPLAT_AUTO = 0, CFS_SPLAT_DIRECT = 1, CFS_SPLAT_BINNED = 2 };
 
@@ -175,18 +175,28 @@ int cfs_chaos_game(const cfs_system *sys, const cfs_run *run,
                    uint8_t *last_index, uint8_t *indices, void *workspace,
                    size_t workspace_bytes, void *stream);
 
+/* Workspace in bytes that cfs_splat needs for this system, run and image. */
+size_t cfs_splat_workspace(const cfs_system *sys, const cfs_run *run,
+                           const cfs_image *img, float sigma_px);
+
 /* Differentiable form, forward (Section 4: automatic generation of the
  * primitive's distribution with autodiff-like tools): the chaos game of a 2D
- * affine system with the identity transform, splatted with the separable
- * shifted-truncated Gaussian g(d) = exp(-d^2/2s^2) - exp(-9/2) for |d| < 3s
- * (s = sigma_px, d = pixel centre - point, in pixels) into an FP32 density
- * img (kind CFS_IMAGE_F32_DENSITY) that ACCUMULATES sum(w) / (N (T - B)).
- *   ckpt: device, nullable; float [n_iters / ckpt_every + 1][n_points][2]:
- *     positions at iterations 0, c, 2c, ... (c = ckpt_every >= 1) that the
- *     backward pass recomputes its segments from.
- * Supports sigma_px in (0, 2.5] (at most 16 taps per axis). */
+ * affine system with the identity transform, FP32 positions, splatted with
+ * the separable shifted-truncated Gaussian
+ *   g(d) = exp(-d^2 / (2 s^2)) - exp(-9/2) for |d| < 3 s, else 0
+ * (s = sigma_px; d = pixel centre - point, in pixels; pixel (i, j) gets
+ * g(i + 0.5 - x) g(j + 0.5 - y); taps off the image are skipped) into the
+ * FP32 density img (kind CFS_IMAGE_F32_DENSITY, one channel), which
+ * ACCUMULATES sum(w) / (N (T - B)).  The order of FP32 additions is not
+ * fixed, so results agree with any other order up to rounding.
+ *   ckpt: device, nullable; float [ceil(n_iters / ckpt_every)][n_points][2]:
+ *     positions at iterations 0, c, 2c, ... (c = ckpt_every in 1..16), from
+ *     which cfs_splat_backward recomputes its segments.
+ *   workspace: device, cfs_splat_workspace() bytes, 256-byte aligned.
+ * sigma_px in (0, 2.5]. */
 int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
-              float sigma_px, float *ckpt, int32_t ckpt_every, void *stream);
+              float sigma_px, float *ckpt, int32_t ckpt_every, void *workspace,
+              size_t workspace_bytes, void *stream);
 
 /* Workspace in bytes for cfs_splat_backward. */
 size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run);
@@ -196,10 +206,12 @@ size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run);
  * checkpoints, recompute each trajectory segment and run the adjoint
  *   lam_T = s_T, lam_t = s_t + A_{k_{t+1}}^T lam_{t+1},
  *   dL/dA_{k_t} += lam_t p_{t-1}^T, dL/db_{k_t} += lam_t
- * (s_t = dL/dp_t through the splat of step t).  grad (device float
- * [n_maps][6] = a00 a01 a10 a11 b0 b1) is OVERWRITTEN; the reduction is
- * deterministic (fixed order, no floating-point atomics).
- * ckpt may be NULL: segments are then recomputed from the initial points. */
+ * (s_t = dL/dp_t through the splat of step t; zero for t <= B).
+ * grad (device float [n_maps][6] = a00 a01 a10 a11 b0 b1) is OVERWRITTEN;
+ * the reduction is deterministic (per-lane sums, then a fixed-order tree and a
+ * fixed-order sum over workgroups; no floating-point atomics).  ckpt must be
+ * the forward's checkpoints for the same system, run and ckpt_every (1..16).
+ * Systems of at most 8 maps. */
 int cfs_splat_backward(const cfs_system *sys, const cfs_run *run,
                        const cfs_image *img, float sigma_px,
                        const float *dL_dD, const float *ckpt,
@@ -207,51 +219,64 @@ int cfs_splat_backward(const cfs_system *sys, const cfs_run *run,
                        size_t workspace_bytes, void *stream);
 
 /* Batched form: many heterogeneous systems (animation frames, different map
- * counts, point counts and image sizes) rendered by ONE persistent kernel
- * launch captured in a HIP graph.  Each instance renders exactly what
- * cfs_chaos_game renders for it (same streams, same device functions). */
+ * counts, point counts and image sizes) rendered by persistent kernels inside
+ * ONE HIP graph launch (abstract and Section 4 of the paper: animation).  Each
+ * instance renders exactly what cfs_chaos_game renders for it (same random
+ * streams, same device functions, FP32 or FP64 positions per instance), so
+ * its image is bit-identical to the plain call's. */
 typedef struct cfs_batch_item {
   cfs_system sys;  /* 2D, identity transform, up to CFS_MAX_MAPS maps */
-  cfs_run run;     /* run.instance selects the instance's random streams */
-  cfs_image img;   /* CFS_IMAGE_U32_COUNT, one channel, caller-owned data */
+  cfs_run run;     /* run.instance selects the instance's random streams;
+                      splat_path is ignored (the plan decides) */
+  cfs_image img;   /* CFS_IMAGE_U32_COUNT, 1 or n_maps channels, caller-owned
+                      data that must stay valid while the batch exists */
 } cfs_batch_item;
 
-/* Schedule of a batch: chunk = points per work item; block = threads per
- * workgroup; grid = persistent workgroups (0 = one per compute unit times
- * the occupancy); lds_limit = largest image (pixels) rendered through an
- * LDS-private tile (0 = never). */
+/* Schedule of a batch.  blocks_per_item: 512-point blocks per work item
+ * popped from the device queue (>= 1); emit_grid: persistent workgroups of
+ * the chaos kernel (0 = two per compute unit); acc_grid: persistent
+ * workgroups of the tile-accumulate kernel (0 = two per compute unit);
+ * splat_path: CFS_SPLAT_BINNED or CFS_SPLAT_DIRECT (CFS_SPLAT_AUTO = binned). */
 typedef struct cfs_plan {
-  int32_t chunk;
-  int32_t block;
-  int32_t grid;
-  int32_t lds_limit;
+  int32_t blocks_per_item;
+  int32_t emit_grid;
+  int32_t acc_grid;
+  int32_t splat_path;
 } cfs_plan;
 
 typedef struct cfs_batch cfs_batch; /* opaque, library-owned */
 
-/* Build a batch: copies the descriptors into library-owned device memory
- * and plans the work queue.  plan NULL = autotuned defaults.  The images
- * are cleared by every cfs_batch_run. */
+/* Build a batch on the current device: copies the descriptors into
+ * library-owned device memory, lays out the work queues (one item per
+ * blocks_per_item blocks of an instance; one accumulate item per image tile)
+ * and allocates the records of the binned splat.  plan NULL = defaults
+ * (use cfs_autotune to pick one).  *out receives the handle. */
 int cfs_batch_create(const cfs_batch_item *items, int32_t n_items,
                      const cfs_plan *plan, cfs_batch **out);
 
-/* Enqueue the whole batch on `stream`: the first call captures {clear the
- * images, reset the work queue, persistent kernel} into a HIP graph; later
- * calls replay it. */
+/* Enqueue the whole batch on `stream`: clear every image, reset the work
+ * queues, run the persistent chaos kernel and the persistent accumulate
+ * kernel.  The first call captures these into a HIP graph (on a library
+ * stream); every call launches that graph on `stream`.  Calls on one batch
+ * must not overlap (they share the queues and records). */
 int cfs_batch_run(cfs_batch *batch, void *stream);
 
-/* Replace instance `index`'s system (same map count; e.g. the next
- * animation frame) without re-capturing the graph.  Ordered on `stream`. */
+/* Replace instance `index`'s map table and probabilities (same map count;
+ * e.g. the next animation frame) without re-capturing the graph.  The new
+ * table is written by a kernel ordered on `stream`. */
 int cfs_batch_update(cfs_batch *batch, int32_t index, const cfs_system *sys,
                      void *stream);
 
 /* The plan a batch uses. */
 int cfs_batch_plan(const cfs_batch *batch, cfs_plan *out);
 
+/* Free the batch (waits for the device to finish its work first). */
 void cfs_batch_destroy(cfs_batch *batch);
 
-/* Project-written autotuner: times candidate plans for this batch with HIP
- * events on `stream` and writes the fastest to *out. */
+/* Project-written autotuner: builds the batch with each candidate plan (both
+ * splat paths, several work-item sizes and accumulate grids), times graph
+ * replays with HIP events on `stream`, and writes the fastest plan to *out.
+ * The images are overwritten by the trial runs. */
 int cfs_autotune(const cfs_batch_item *items, int32_t n_items, cfs_plan *out,
                  void *stream);
 

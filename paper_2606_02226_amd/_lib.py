@@ -27,7 +27,7 @@ SPLAT_PATHS = {"auto": 0, "direct": 1, "binned": 2}
 # Every symbol include/cfs.h declares.
 EXPORTS = (
     "cfs_version", "cfs_last_error", "cfs_image_clear", "cfs_chaos_game_workspace",
-    "cfs_chaos_game", "cfs_splat", "cfs_splat_backward_workspace",
+    "cfs_chaos_game", "cfs_splat_workspace", "cfs_splat", "cfs_splat_backward_workspace",
     "cfs_splat_backward", "cfs_batch_create", "cfs_batch_run", "cfs_batch_update",
     "cfs_batch_plan", "cfs_batch_destroy", "cfs_autotune", "cfs_philox_dump",
 )
@@ -59,8 +59,8 @@ class CfsBatchItem(C.Structure):
 
 
 class CfsPlan(C.Structure):
-    _fields_ = [("chunk", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
-                ("lds_limit", C.c_int32)]
+    _fields_ = [("blocks_per_item", C.c_int32), ("emit_grid", C.c_int32),
+                ("acc_grid", C.c_int32), ("splat_path", C.c_int32)]
 
 
 _lib = None
@@ -91,8 +91,11 @@ def load():
     lib.cfs_chaos_game_workspace.restype = C.c_size_t
     lib.cfs_chaos_game.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun),
                                    C.POINTER(CfsImage), P, P, P, P, C.c_size_t, P]
+    lib.cfs_splat_workspace.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun),
+                                        C.POINTER(CfsImage), C.c_float]
+    lib.cfs_splat_workspace.restype = C.c_size_t
     lib.cfs_splat.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun), C.POINTER(CfsImage),
-                              C.c_float, P, C.c_int32, P]
+                              C.c_float, P, C.c_int32, P, C.c_size_t, P]
     lib.cfs_splat_backward_workspace.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun)]
     lib.cfs_splat_backward_workspace.restype = C.c_size_t
     lib.cfs_splat_backward.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun),

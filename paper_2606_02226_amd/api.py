@@ -164,3 +164,148 @@ def philox_dump(seed, ctrs, stream=None):
                               C.c_uint64(ctrs.shape[0]), _stream_handle(stream)),
           "cfs_philox_dump")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Differentiable form
+# ---------------------------------------------------------------------------
+def n_checkpoints(n_iters, every):
+    return (int(n_iters) + int(every) - 1) // int(every)
+
+
+def splat(system, run, image, sigma_px, *, ckpt=None, ckpt_every=8, workspace=None,
+          stream=None):
+    """Gaussian soft splat (cfs_splat) into an f32_density ``image``.
+
+    ``ckpt`` is an optional float32 device tensor
+    [ceil(T / ckpt_every)][N][2] that receives the checkpoints."""
+    lib = _lib.load()
+    sysc = system if isinstance(system, System) else System(system)
+    runc = run_struct(run, "f32")
+    need = int(lib.cfs_splat_workspace(C.byref(sysc.struct), C.byref(runc),
+                                       C.byref(image.struct), C.c_float(sigma_px)))
+    ws = workspace
+    if need and (ws is None or ws.numel() < need):
+        ws = torch.empty(need, dtype=torch.uint8, device=image.data.device)
+    rc = lib.cfs_splat(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
+                       C.c_float(sigma_px), _ptr(ckpt), C.c_int32(int(ckpt_every)),
+                       _ptr(ws if need else None), C.c_size_t(need), _stream_handle(stream))
+    check(rc, "cfs_splat")
+    return image
+
+
+def splat_backward(system, run, image, sigma_px, dL_dD, ckpt, ckpt_every=8, grad=None,
+                   stream=None):
+    """Adjoint of the Gaussian splat (cfs_splat_backward): returns the float32
+    device gradient [n_maps][6] = (a00, a01, a10, a11, b0, b1)."""
+    lib = _lib.load()
+    sysc = system if isinstance(system, System) else System(system)
+    runc = run_struct(run, "f32")
+    need = int(lib.cfs_splat_backward_workspace(C.byref(sysc.struct), C.byref(runc)))
+    dev = dL_dD.device
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if grad is None:
+        grad = torch.empty((sysc.n_maps, 6), dtype=torch.float32, device=dev)
+    g = dL_dD.contiguous()
+    rc = lib.cfs_splat_backward(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
+                                C.c_float(sigma_px), _ptr(g), _ptr(ckpt),
+                                C.c_int32(int(ckpt_every)), _ptr(grad), _ptr(ws),
+                                C.c_size_t(need), _stream_handle(stream))
+    check(rc, "cfs_splat_backward")
+    return grad
+
+
+def theta_to_system(theta, like=None, prob=None):
+    """System dict of a 2D affine IFS from parameters [n][6] =
+    (a00, a01, a10, a11, b0, b1) (a host copy is taken: the map table travels
+    in kernel arguments)."""
+    th = theta.detach().to("cpu", torch.float32).numpy() if torch.is_tensor(theta) \
+        else np.asarray(theta, np.float32)
+    return {"dim": 2, "A": th[:, :4].reshape(-1, 2, 2).copy(), "b": th[:, 4:].copy(),
+            "prob": prob if like is None else like.get("prob"),
+            "final_kind": "identity", "final_params": np.zeros(24, np.float32)}
+
+
+# ---------------------------------------------------------------------------
+# Batched form
+# ---------------------------------------------------------------------------
+def _plan_struct(plan):
+    if plan is None:
+        return None
+    p = _lib.CfsPlan()
+    p.blocks_per_item = int(plan.get("blocks_per_item", 1))
+    p.emit_grid = int(plan.get("emit_grid", 0))
+    p.acc_grid = int(plan.get("acc_grid", 0))
+    p.splat_path = _lib.SPLAT_PATHS[plan.get("splat_path", "binned")]
+    return p
+
+
+def _plan_dict(p):
+    names = {v: k for k, v in _lib.SPLAT_PATHS.items()}
+    return {"blocks_per_item": p.blocks_per_item, "emit_grid": p.emit_grid,
+            "acc_grid": p.acc_grid, "splat_path": names[p.splat_path]}
+
+
+def _batch_items(entries, images, precision):
+    n = len(entries)
+    items = (_lib.CfsBatchItem * n)()
+    keep = []
+    for i, (w, img) in enumerate(zip(entries, images)):
+        s = System(w["system"])
+        keep.append(s)
+        items[i].sys = s.struct
+        items[i].run = run_struct(w["run"], precision)
+        items[i].img = img.struct
+    return items, keep
+
+
+class Batch:
+    """A batch of instances (workload dicts with system/run/image) rendered by
+    one HIP-graph launch per ``run()`` into ``images`` (api.Image objects that
+    must outlive the batch)."""
+
+    def __init__(self, entries, images, plan=None, precision="f32"):
+        lib = _lib.load()
+        self.images = list(images)
+        items, keep = _batch_items(entries, self.images, precision)
+        handle = C.c_void_p()
+        ps = _plan_struct(plan)
+        check(lib.cfs_batch_create(items, len(entries), None if ps is None else C.byref(ps),
+                                   C.byref(handle)), "cfs_batch_create")
+        self._h = handle
+        self._keep = keep
+
+    def run(self, stream=None):
+        check(_lib.load().cfs_batch_run(self._h, _stream_handle(stream)), "cfs_batch_run")
+
+    def update(self, index, system, stream=None):
+        s = System(system)
+        check(_lib.load().cfs_batch_update(self._h, int(index), C.byref(s.struct),
+                                           _stream_handle(stream)), "cfs_batch_update")
+
+    def plan(self):
+        p = _lib.CfsPlan()
+        check(_lib.load().cfs_batch_plan(self._h, C.byref(p)), "cfs_batch_plan")
+        return _plan_dict(p)
+
+    def close(self):
+        if self._h:
+            _lib.load().cfs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(entries, images, precision="f32", stream=None):
+    """Time the candidate plans on this batch (cfs_autotune); returns the
+    fastest plan as a dict.  Overwrites the images."""
+    lib = _lib.load()
+    items, keep = _batch_items(entries, images, precision)
+    p = _lib.CfsPlan()
+    check(lib.cfs_autotune(items, len(entries), C.byref(p), _stream_handle(stream)),
+          "cfs_autotune")
+    return _plan_dict(p)

@@ -256,7 +256,7 @@ size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 size_t binned_workspace(const cfs_run *run, const cfs_image *img) {
   const uint32_t elems = static_cast<uint32_t>(img->width) * img->height * img->channels;
   const BinPlan bp = bin_plan(binned_slice(run), run->n_iters, run->burn_in, elems);
-  return align_up(bp.records_bytes) + align_up(bp.table_bytes);
+  return align_up(bp.records_bytes) + 2 * align_up(bp.table_bytes);
 }
 
 }  // namespace
@@ -303,7 +303,8 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
   }
   const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
   if (run->splat_path == CFS_SPLAT_BINNED && elems > static_cast<uint64_t>(kMaxTiles) * kTileElems)
-    return fail(CFS_E_UNSUPPORTED, "binned splat handles images of at most 2^26 elements");
+    return fail(CFS_E_UNSUPPORTED, "binned splat handles images of at most %u elements",
+                static_cast<unsigned>(kMaxTiles * kTileElems));
   const size_t align = run->precision == CFS_PREC_F64 ? 8 : 4;
   if (final_points && reinterpret_cast<uintptr_t>(final_points) % align)
     return fail(CFS_E_INVALID, "final_points is not %zu-byte aligned", align);
@@ -349,7 +350,9 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
     if (last_index) sj.out.last_index = last_index + done;
     if (indices) sj.out.indices = indices + static_cast<size_t>(done) * run->n_iters;
     sj.ba.records = static_cast<uint16_t *>(workspace);
-    sj.ba.tile_start = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + align_up(bp.records_bytes));
+    char *tables = static_cast<char *>(workspace) + align_up(bp.records_bytes);
+    sj.ba.chunk_start = reinterpret_cast<uint32_t *>(tables);
+    sj.ba.tile_start = reinterpret_cast<uint32_t *>(tables + align_up(bp.table_bytes));
     sj.ba.n_chunks = bp.n_chunks;
     sj.ba.flushes = bp.flushes;
     sj.ba.n_tiles = bp.n_tiles;

@@ -1,0 +1,167 @@
+// cfs_api_gauss.hip -- C ABI of the differentiable form (cfs_splat,
+// cfs_splat_backward and their workspace queries): validation, packing and
+// point-range slicing of the Gaussian splat.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "cfs.h"
+#include "cfs_api_internal.hpp"
+#include "cfs_host.hpp"
+
+using namespace cfs;
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+int validate_gauss(const cfs_system *sys, const cfs_run *run, const cfs_image *img, float sigma) {
+  int rc = validate_system(sys);
+  if (!rc) rc = validate_run(run);
+  if (!rc) rc = validate_window(img);
+  if (rc) return rc;
+  if (sys->dim != 2 || sys->final_kind != CFS_FINAL_IDENTITY)
+    return fail(CFS_E_UNSUPPORTED, "the Gaussian splat takes 2D systems with the identity transform");
+  if (run->precision != CFS_PREC_F32)
+    return fail(CFS_E_UNSUPPORTED, "the Gaussian splat computes positions in FP32");
+  if (img->kind != CFS_IMAGE_F32_DENSITY || img->channels != 1)
+    return fail(CFS_E_INVALID, "the Gaussian splat renders a one-channel F32_DENSITY image");
+  if (!(sigma > 0.0f) || sigma > 2.5f) return fail(CFS_E_INVALID, "sigma_px must be in (0, 2.5]");
+  const uint64_t tiles = static_cast<uint64_t>((img->width + kGTile - 1) / kGTile) *
+                         ((img->height + kGTile - 1) / kGTile);
+  if (tiles > static_cast<uint64_t>(kGMaxTiles))
+    return fail(CFS_E_UNSUPPORTED, "the Gaussian splat handles at most %d tiles of %dx%d pixels",
+                kGMaxTiles, kGTile, kGTile);
+  return CFS_OK;
+}
+
+// Points per forward launch: at most 2^27 records (1 GiB) of workspace.
+uint32_t gauss_slice(const cfs_run *run) {
+  const uint64_t flushes = std::max<uint64_t>((run->n_iters - run->burn_in + kGSlots - 1) / kGSlots, 1);
+  uint64_t blocks = (1ull << 27) / (flushes * kGCap);
+  if (blocks < 1) blocks = 1;
+  uint64_t pts = blocks * kGBlock;
+  if (pts > run->n_points) pts = run->n_points;
+  return static_cast<uint32_t>(std::max<uint64_t>(pts, 1));
+}
+
+GaussParams make_gauss_params(const cfs_run *run, const cfs_image *img, float sigma) {
+  GaussParams gp{};
+  gp.sigma = sigma;
+  gp.R = 3.0f * sigma;
+  gp.inv2s2 = 1.0f / (2.0f * sigma * sigma);
+  gp.inv_s2 = 1.0f / (sigma * sigma);
+  gp.cutoff = std::exp(-gp.R * gp.R * gp.inv2s2);
+  gp.taps = static_cast<int32_t>(std::ceil(2.0f * gp.R));
+  gp.weight = static_cast<float>(1.0 / (static_cast<double>(run->n_points) *
+                                        static_cast<double>(run->n_iters - run->burn_in)));
+  gp.width = img->width;
+  gp.height = img->height;
+  gp.tiles_x = (img->width + kGTile - 1) / kGTile;
+  gp.tiles_y = (img->height + kGTile - 1) / kGTile;
+  for (int a = 0; a < 2; ++a) {
+    gp.lo[a] = img->lo[a];
+    gp.scale[a] = static_cast<float>(static_cast<double>(a == 0 ? img->width : img->height) /
+                                     (static_cast<double>(img->hi[a]) - static_cast<double>(img->lo[a])));
+  }
+  return gp;
+}
+
+}  // namespace
+
+extern "C" size_t cfs_splat_workspace(const cfs_system *sys, const cfs_run *run,
+                                      const cfs_image *img, float sigma_px) {
+  if (validate_gauss(sys, run, img, sigma_px)) return 0;
+  if (run->n_iters == run->burn_in || run->n_points == 0) return 0;
+  const GaussPlan p = gauss_plan(gauss_slice(run), run->n_iters, run->burn_in, img->width, img->height);
+  return align_up(p.records_bytes) + align_up(p.table_bytes);
+}
+
+extern "C" int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
+                         float sigma_px, float *ckpt, int32_t ckpt_every, void *workspace,
+                         size_t workspace_bytes, void *stream) {
+  clear_error();
+  int rc = validate_gauss(sys, run, img, sigma_px);
+  if (rc) return rc;
+  if (ckpt && (ckpt_every < 1 || ckpt_every > kMaxSeg))
+    return fail(CFS_E_INVALID, "ckpt_every must be in 1..%d", kMaxSeg);
+  if (ckpt && reinterpret_cast<uintptr_t>(ckpt) % 8) return fail(CFS_E_INVALID, "ckpt is not 8-byte aligned");
+  const size_t need = cfs_splat_workspace(sys, run, img, sigma_px);
+  if (need && (!workspace || workspace_bytes < need))
+    return fail(CFS_E_WORKSPACE, "cfs_splat needs %zu bytes of workspace, got %zu", need,
+                workspace ? workspace_bytes : static_cast<size_t>(0));
+  if (workspace && reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(CFS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  GaussJob job;
+  std::memset(&job, 0, sizeof job);
+  rc = pack_table<2>(sys, &job.mt, &job.equal);
+  if (rc) return rc;
+  job.gp = make_gauss_params(run, img, sigma_px);
+  job.dens = static_cast<float *>(img->data);
+  job.dropped = img->dropped;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const RunArgs ra = make_run_args(run);
+  const bool no_splats = run->n_iters == run->burn_in;
+  const uint32_t slice = gauss_slice(run);
+  for (uint32_t done = 0; done < run->n_points; done += slice) {
+    const uint32_t pts = std::min(slice, run->n_points - done);
+    GaussJob j = job;
+    j.ra = ra;
+    j.ra.n_points = pts;
+    j.ra.point_offset = run->point_offset + done;
+    const GaussPlan p = gauss_plan(pts, run->n_iters, run->burn_in, img->width, img->height);
+    j.gb.records = static_cast<float2 *>(workspace);
+    j.gb.tile_start = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + align_up(p.records_bytes));
+    j.gb.n_chunks = no_splats ? 0 : p.n_chunks;
+    j.gb.flushes = p.flushes;
+    j.gb.n_tiles = p.n_tiles;
+    j.ck.ckpt = ckpt ? ckpt + 2 * static_cast<size_t>(done) : nullptr;
+    j.ck.every = ckpt_every;
+    j.ck.stride = run->n_points;
+    if (no_splats && !ckpt) continue;
+    rc = device_status(launch_splat_forward(j, s), "cfs_splat");
+    if (rc) return rc;
+  }
+  return CFS_OK;
+}
+
+extern "C" size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run) {
+  if (validate_system(sys) || validate_run(run)) return 0;
+  const uint32_t blocks = (run->n_points + kGBwdBlock - 1) / kGBwdBlock;
+  const int ng = sys->n_maps <= 4 ? 4 : 8;
+  return align_up(static_cast<size_t>(std::max<uint32_t>(blocks, 1)) * ng * 6 * sizeof(float));
+}
+
+extern "C" int cfs_splat_backward(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
+                                  float sigma_px, const float *dL_dD, const float *ckpt,
+                                  int32_t ckpt_every, float *grad, void *workspace,
+                                  size_t workspace_bytes, void *stream) {
+  clear_error();
+  int rc = validate_gauss(sys, run, img, sigma_px);
+  if (rc) return rc;
+  if (sys->n_maps > 8) return fail(CFS_E_UNSUPPORTED, "the adjoint handles systems of at most 8 maps");
+  if (!dL_dD || !ckpt || !grad) return fail(CFS_E_INVALID, "dL_dD, ckpt and grad are required");
+  if (ckpt_every < 1 || ckpt_every > kMaxSeg)
+    return fail(CFS_E_INVALID, "ckpt_every must be in 1..%d", kMaxSeg);
+  if ((reinterpret_cast<uintptr_t>(dL_dD) | reinterpret_cast<uintptr_t>(grad)) % 4 ||
+      reinterpret_cast<uintptr_t>(ckpt) % 8)
+    return fail(CFS_E_INVALID, "misaligned dL_dD, ckpt or grad");
+  const size_t need = cfs_splat_backward_workspace(sys, run);
+  if (!workspace || workspace_bytes < need)
+    return fail(CFS_E_WORKSPACE, "cfs_splat_backward needs %zu bytes of workspace, got %zu", need,
+                workspace ? workspace_bytes : static_cast<size_t>(0));
+  GaussJob job;
+  std::memset(&job, 0, sizeof job);
+  rc = pack_table<2>(sys, &job.mt, &job.equal);
+  if (rc) return rc;
+  job.ra = make_run_args(run);
+  job.gp = make_gauss_params(run, img, sigma_px);
+  job.ck.ckpt = const_cast<float *>(ckpt);
+  job.ck.every = ckpt_every;
+  job.ck.stride = run->n_points;
+  job.dLdD = dL_dD;
+  job.partials = static_cast<float *>(workspace);
+  job.grad = grad;
+  return device_status(launch_splat_backward(job, static_cast<hipStream_t>(stream)),
+                       "cfs_splat_backward");
+}

@@ -1,0 +1,60 @@
+// cfs_batch_dev.hpp -- descriptors and launch arguments of the batched form.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cfs_params.hpp"
+
+namespace cfs {
+
+constexpr int kClearParts = 16;
+constexpr int kQueues = 3;  // FP32 items, FP64 items, accumulate items
+
+// One instance as the persistent kernels see it (device memory).
+struct InstDesc {
+  MapTable<2> mt;
+  Window win;
+  RunArgs ra;
+  uint32_t *img;
+  unsigned long long *dropped;
+  uint32_t elems, n_tiles, flushes, n_chunks;
+  uint64_t rec_base;    // first record of the instance's chunks
+  uint64_t table_base;  // first word of the instance's run-start tables
+  int32_t equal;
+  int32_t precision;    // 0 = FP32 positions, 1 = FP64
+};
+
+struct EmitItem {
+  uint32_t inst, first_block, n_blocks;
+};
+
+struct AccItem {
+  uint32_t inst, tile;
+};
+
+struct TransItem {
+  uint32_t inst, bx, by;  // 64x64 block of the instance's table transpose
+};
+
+struct BatchLaunch {
+  InstDesc *desc;
+  uint32_t n_inst;
+  const EmitItem *items;  // FP32 instances' items, then FP64 instances' items
+  uint32_t n_items32, n_items64;
+  const AccItem *acc;
+  uint32_t n_acc;
+  uint32_t *queues;  // [kQueues]
+  const TransItem *trans;
+  uint32_t n_trans;
+  uint16_t *records;
+  uint32_t *ctables;  // [chunk][tile + 1] per instance
+  uint32_t *tables;   // [tile + 1][chunk] per instance
+  uint32_t emit_grid, acc_grid;
+  bool direct;
+};
+
+hipError_t launch_batch(const BatchLaunch &b, hipStream_t stream);
+hipError_t launch_batch_set_table(InstDesc *desc, uint32_t index, const MapTable<2> &mt, bool equal,
+                                  hipStream_t stream);
+
+}  // namespace cfs

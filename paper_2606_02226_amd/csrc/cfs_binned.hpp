@@ -1,0 +1,226 @@
+// cfs_binned.hpp -- device functions of the binned integer splat, shared by
+// the plain binned kernels and the batched persistent kernels (so a batched
+// instance runs exactly the code of a plain run).
+#pragma once
+
+#include "cfs_device.hpp"
+
+namespace cfs {
+
+constexpr uint32_t kInvalid = 0xFFFFFFFFu;
+constexpr int kWaves = kBinBlock / 64;
+
+// Exclusive prefix sum of a[0..n) in place (n <= kMaxTiles), returns the
+// total.  Thread i owns kScanPer consecutive entries.  Every thread of the
+// workgroup must call it.
+constexpr int kScanPer = (kMaxTiles + kBinBlock - 1) / kBinBlock;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t i0 = static_cast<uint32_t>(tid) * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    v[q] = i0 + q < n ? a[i0 + q] : 0u;
+    s += v[q];
+  }
+  uint32_t incl = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t x = lane < kWaves ? wsum[lane] : 0u;
+    uint32_t xi = x;
+#pragma unroll
+    for (int d = 1; d < kWaves; d <<= 1) {
+      const uint32_t y = __shfl_up(xi, d, 64);
+      if (lane >= d) xi += y;
+    }
+    if (lane < kWaves) wsum[lane] = xi - x;
+    if (lane == kWaves - 1) wsum[kWaves] = xi;
+  }
+  __syncthreads();
+  uint32_t run = wsum[w] + incl - s;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    if (i0 + q < n) a[i0 + q] = run;
+    run += v[q];
+  }
+  const uint32_t total = wsum[kWaves];
+  __syncthreads();
+  return total;
+}
+
+// Sort the stage of one chunk by tile and write it out (all threads call it).
+// On entry cnt[t] holds the number of stage records of tile t (counted as
+// they were staged); the counts are scanned into tile starts, each record
+// takes its slot from an LDS cursor per tile, and the sorted stage is written
+// out.  cnt[] is zero on return.
+__device__ inline void flush_chunk(uint32_t *stage, uint32_t *cnt, uint32_t *wsum, int used_slots,
+                                   uint32_t chunk, const BinArgs &ba) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const uint32_t total = block_exclusive_scan(cnt, ba.n_tiles, wsum);
+  const uint32_t base = chunk * kChunkCap;
+  uint32_t *row = ba.chunk_start + static_cast<size_t>(chunk) * (ba.n_tiles + 1);
+  for (uint32_t t = tid; t <= ba.n_tiles; t += kBinBlock) row[t] = base + (t < ba.n_tiles ? cnt[t] : total);
+  uint32_t e[kBinSlots];
+#pragma unroll
+  for (int i = 0; i < kBinSlots; ++i) e[i] = i < used_slots ? stage[i * kBinBlock + tid] : kInvalid;
+  __syncthreads();  // all stage entries read and table column written
+#pragma unroll
+  for (int i = 0; i < kBinSlots; ++i)
+    if (e[i] != kInvalid) stage[atomicAdd(&cnt[e[i] >> kTileBits], 1u)] = e[i];
+  __syncthreads();
+  // two 16-bit records per 32-bit store (chunk bases are even)
+  uint32_t *out32 = reinterpret_cast<uint32_t *>(ba.records + base);
+  for (uint32_t i = tid; 2 * i < total; i += kBinBlock) {
+    const uint32_t lo = stage[2 * i] & (kTileElems - 1);
+    const uint32_t hi = 2 * i + 1 < total ? (stage[2 * i + 1] & (kTileElems - 1)) : 0xFFFFu;
+    out32[i] = lo | (hi << 16);
+  }
+  for (uint32_t t = tid; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
+  __syncthreads();
+}
+
+// One block of kBinBlock points (block index `block` of the run): the chaos
+// game of each lane's point with the binned splat.  table/th hold the map
+// table in LDS; cnt[0 .. n_tiles) must be zero on entry and is zero on exit.
+// Every thread of the workgroup calls it (it holds barriers).
+template <typename real, int DIM, int FINAL, int SEL>
+__device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_maps, int n_search,
+                                   int top_step, const Window &win, const RunArgs &ra,
+                                   const float *fparams, const BinArgs &ba, const Outputs &out,
+                                   uint32_t block, uint32_t *stage, uint32_t *cnt, uint32_t *wsum) {
+  const int tid = threadIdx.x;
+  const uint32_t n = block * kBinBlock + tid;
+  const bool active = n < ra.n_points;
+  const uint32_t pid = ra.point_offset + (active ? n : 0u);
+  const uint32_t T = ra.n_iters, B = ra.burn_in;
+  const uint32_t plane = static_cast<uint32_t>(win.width) * static_cast<uint32_t>(win.height);
+
+  real p[DIM];
+  initial_point<real, DIM>(pid, ra.instance, ra.k0, ra.k1, p);
+  int k = 0;
+  uint32_t dropped = 0;
+  int slot = 0;
+  uint32_t chunk = block * ba.flushes;
+
+  for (uint32_t t0 = 0; t0 < T; t0 += 4) {
+    const Block4 blk = philox10(pid, t0 >> 2, ra.instance, 0u, ra.k0, ra.k1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t = t0 + j + 1;
+      if (t > T) break;
+      const uint32_t u = word_of(blk, j);
+      k = select_index<SEL>(u, th, n_maps, n_search, top_step);
+      if (active && out.indices)
+        out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
+      apply_map<real, DIM>(table, k, p);
+      if (t > B) {
+        uint32_t e = kInvalid;
+        if (active) {
+          real q[2];
+          real depth = static_cast<real>(0);
+          final_transform<real, FINAL, DIM>(fparams, p, q, &depth);
+          int ix;
+          const int pix = bin_pixel<real>(q, win, &ix);
+          if (pix >= 0)
+            e = (win.by_index ? static_cast<uint32_t>(k) * plane : 0u) + static_cast<uint32_t>(pix);
+          else
+            ++dropped;
+        }
+        stage[slot * kBinBlock + tid] = e;
+        if (e != kInvalid) atomicAdd(&cnt[e >> kTileBits], 1u);
+        if (++slot == kBinSlots) {
+          flush_chunk(stage, cnt, wsum, slot, chunk, ba);
+          slot = 0;
+          ++chunk;
+        }
+      }
+    }
+  }
+  if (slot > 0) flush_chunk(stage, cnt, wsum, slot, chunk, ba);
+
+  if (!active) return;
+  if (out.final_points) {
+    real *fp = static_cast<real *>(out.final_points) + static_cast<size_t>(n) * DIM;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) fp[c] = p[c];
+  }
+  if (out.last_index) out.last_index[n] = static_cast<uint8_t>(k);
+  if (out.dropped && dropped)
+    __hip_atomic_fetch_add(out.dropped, static_cast<unsigned long long>(dropped),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Image tile t of one run: LDS histogram of the tile's records from every
+// chunk, then added into the image (the workgroup owns the tile).  Each lane
+// walks the run of one chunk with 8-byte loads (4 records), four loads in
+// flight; runs start anywhere, so loads start at the 4-record boundary below
+// the run and records outside [start, end) are skipped.  Every thread of the
+// workgroup calls it; `tile` is kTileElems words of LDS.
+__device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
+                                       const uint32_t *__restrict__ tile_start, uint32_t n_chunks,
+                                       uint32_t elems, uint32_t *__restrict__ img, uint32_t t,
+                                       uint32_t *tile) {
+  const int tid = threadIdx.x;
+  for (uint32_t i = tid; i < kTileElems; i += kAccBlock) tile[i] = 0u;
+  __syncthreads();
+  const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
+  const uint32_t *row1 = row0 + n_chunks;
+  for (uint32_t c = tid; c < n_chunks; c += kAccBlock) {
+    const uint32_t s = row0[c];
+    const uint32_t e = row1[c];
+    for (uint32_t i = s & ~3u; i < e; i += 16u) {
+      uint2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t at = i + 4u * u;
+        v[u] = at < e ? *reinterpret_cast<const uint2 *>(rec + at) : make_uint2(0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t r4[4] = {v[u].x & 0xFFFFu, v[u].x >> 16, v[u].y & 0xFFFFu, v[u].y >> 16};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const uint32_t idx = i + 4u * u + m;
+          if (idx >= s && idx < e) atomicAdd(&tile[r4[m]], 1u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t base = t * kTileElems;
+  const uint32_t len = min(kTileElems, elems - base);
+  for (uint32_t i = tid; i < len; i += kAccBlock) {
+    const uint32_t v = tile[i];
+    if (v) img[base + i] += v;
+  }
+  __syncthreads();
+}
+
+// [rows][cols] -> [cols][rows] through 64x64 LDS tiles (one workgroup of
+// 256 threads per tile).
+__device__ inline void transpose_tile(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                      uint32_t rows, uint32_t cols, uint32_t bx, uint32_t by,
+                                      uint32_t (*buf)[65]) {
+  const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (uint32_t r = ty; r < 64; r += 4) {
+    const uint32_t gr = by * 64 + r, gc = bx * 64 + tx;
+    buf[r][tx] = (gr < rows && gc < cols) ? in[static_cast<size_t>(gr) * cols + gc] : 0u;
+  }
+  __syncthreads();
+  for (uint32_t r = ty; r < 64; r += 4) {
+    const uint32_t gc = bx * 64 + r, gr = by * 64 + tx;
+    if (gc < cols && gr < rows) out[static_cast<size_t>(gc) * rows + gr] = buf[tx][r];
+  }
+  __syncthreads();
+}
+
+}  // namespace cfs

@@ -77,6 +77,25 @@ __device__ __forceinline__ int select_table(uint32_t u, const uint32_t *__restri
   return k;
 }
 
+// SEL: kSelTable, kSelEqual (compile-time rule) or kSelRuntime (equal when
+// n_search == 0; used where one kernel serves systems of both kinds).
+constexpr int kSelTable = 0;
+constexpr int kSelEqual = 1;
+constexpr int kSelRuntime = 2;
+
+template <int SEL>
+__device__ __forceinline__ int select_index(uint32_t u, const uint32_t *th, int n_maps, int n_search,
+                                            int top_step) {
+  if constexpr (SEL == kSelEqual) {
+    return select_equal(u, static_cast<uint32_t>(n_maps));
+  } else if constexpr (SEL == kSelTable) {
+    return select_table(u, th, n_search, top_step);
+  } else {
+    return n_search == 0 ? select_equal(u, static_cast<uint32_t>(n_maps))
+                         : select_table(u, th, n_search, top_step);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Map table rows in LDS.  2D FP32 rows are 8 floats (two 16-byte reads);
 // 2D FP64 rows are 6 doubles; 3D rows hold A row-major then b.

@@ -39,6 +39,31 @@ struct BinPlan {
 BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems);
 
 hipError_t launch_chaos_binned(const ChaosJob &job, hipStream_t stream);
+hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,
+                            hipStream_t stream);
+
+struct GaussJob {
+  bool equal;
+  MapTable<2> mt;
+  RunArgs ra;
+  GaussParams gp;
+  GaussBin gb;
+  GaussCkpt ck;
+  float *dens;
+  unsigned long long *dropped;
+  const float *dLdD;
+  float *partials;
+  float *grad;
+};
+
+struct GaussPlan {
+  uint32_t blocks, flushes, n_chunks, n_tiles;
+  int32_t tiles_x, tiles_y;
+  size_t records_bytes, table_bytes;
+};
+GaussPlan gauss_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, int width, int height);
+hipError_t launch_splat_forward(const GaussJob &job, hipStream_t stream);
+hipError_t launch_splat_backward(const GaussJob &job, hipStream_t stream);
 
 hipError_t launch_chaos(const ChaosJob &job, hipStream_t stream);
 hipError_t launch_clear_u32(uint32_t *p, size_t n, hipStream_t stream);

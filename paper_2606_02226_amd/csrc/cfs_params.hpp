@@ -42,25 +42,60 @@ struct RunArgs {
   uint32_t burn_in;
 };
 
-// Binned integer splat: a workgroup of kBinBlock lanes collects kBinSlots
+// Binned integer splat: a workgroup of kBinBlock lanes (two per CU fit in
+// LDS, so one computes while the other sorts) collects kBinSlots
 // splats per lane (one chunk of kChunkCap records), sorts them by image tile
 // of kTileElems elements in LDS and writes each tile's records as a run of
 // 16-bit in-tile offsets; a per-tile kernel then accumulates the runs in LDS.
-constexpr int kBinBlock = 1024;
+constexpr int kBinBlock = 512;
 constexpr int kBinSlots = 24;
 constexpr uint32_t kChunkCap = static_cast<uint32_t>(kBinBlock) * kBinSlots;
-constexpr int kTileBits = 15;
+constexpr int kTileBits = 14;
 constexpr uint32_t kTileElems = 1u << kTileBits;
-constexpr int kMaxTiles = 2048;
-constexpr int kAccBlock = 1024;
+constexpr int kMaxTiles = 2048;  // images of up to 2^25 elements
+constexpr int kAccBlock = 512;
 
 struct BinArgs {
   uint16_t *records;     // [n_chunks][kChunkCap] in-tile offsets, runs by tile
-  uint32_t *tile_start;  // [n_tiles + 1][n_chunks]: absolute record index
+  uint32_t *chunk_start; // [n_chunks][n_tiles + 1]: run starts as the chunks write them
+  uint32_t *tile_start;  // [n_tiles + 1][n_chunks]: the same, transposed for the accumulate
   uint32_t n_chunks;     // chunks of this launch (= blocks * flushes)
   uint32_t flushes;      // chunks per workgroup
   uint32_t n_tiles;
   uint32_t elems;        // image elements (channels * height * width)
+};
+
+// Gaussian splat: 1024-lane workgroups collect kGSlots splats per lane as
+// (x, y) pixel-coordinate records, sorted by 32x32-pixel tile.
+constexpr int kGBlock = 1024;
+constexpr int kGSlots = 12;
+constexpr uint32_t kGCap = static_cast<uint32_t>(kGBlock) * kGSlots;
+constexpr int kGTileLog = 5;
+constexpr int kGTile = 1 << kGTileLog;
+constexpr int kGMaxTiles = 2048;
+constexpr int kGAccBlock = 256;
+constexpr int kGBwdBlock = 256;
+constexpr int kMaxSeg = 16;  // longest checkpoint segment
+
+struct GaussParams {
+  float sigma, inv2s2, inv_s2, cutoff, R;  // R = 3 sigma, cutoff = exp(-R^2/2s^2)
+  float weight;                            // 1 / (N (T - B)) of the whole run
+  int32_t taps;                            // candidate taps per axis
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  float lo[2], scale[2];
+};
+
+struct GaussBin {
+  float2 *records;       // [n_chunks][kGCap] pixel coordinates, runs by tile
+  uint32_t *tile_start;  // [n_tiles + 1][n_chunks]
+  uint32_t n_chunks, flushes, n_tiles;
+};
+
+struct GaussCkpt {
+  float *ckpt;           // [n_ckpt][stride][2] (base already offset to the slice)
+  int32_t every;
+  uint32_t stride;       // points of the whole run
 };
 
 struct Outputs {

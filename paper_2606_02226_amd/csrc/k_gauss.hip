@@ -1,0 +1,472 @@
+// k_gauss.hip -- differentiable form of the chaos game (Section 4 of the
+// paper: the distribution of a primitive could be generated automatically with
+// autodiff-like tools).
+//
+// Forward: the chaos game of a 2D affine system in FP32 splats every iterate
+// with a separable shifted-truncated Gaussian (continuous in the point, so the
+// density is a continuous function of the map parameters).  Like the integer
+// splat, the taps are not applied with device atomics: each splat becomes one
+// (x, y) record, records are sorted in LDS by the 32x32-pixel tile that holds
+// their footprint's first tap, and a per-tile kernel evaluates the taps of the
+// records of its own tile and of its left, upper and upper-left neighbours
+// (a footprint of at most 16 taps spans at most two tiles per axis) into an
+// LDS tile.  Checkpoints of the positions every c iterations are written for
+// the backward pass.
+//
+// Backward: per point, each checkpoint segment is recomputed into registers
+// and swept in reverse with the adjoint
+//   lam_t = s_t + A_{k_{t+1}}^T lam_{t+1},  dA_{k_t} += lam_t p_{t-1}^T,
+//   db_{k_t} += lam_t,
+// where s_t gathers dL/dD over the splat's taps.  Gradients stay in registers
+// per lane and are reduced in a fixed order (no floating-point atomics).
+#include "cfs_device.hpp"
+#include "cfs_host.hpp"
+
+namespace cfs {
+
+constexpr uint32_t kGInvalid = 0xFFFFFFFFu;
+constexpr int kGWaves = kGBlock / 64;
+
+__device__ __forceinline__ bool rec_valid(float2 r) { return __float_as_uint(r.x) != kGInvalid; }
+
+// First tap index of a point at pixel coordinate x: taps i satisfy
+// |i + 0.5 - x| < R, i.e. i > x - R - 0.5.
+__device__ __forceinline__ int first_tap(float x, float R) {
+  return static_cast<int>(floorf(x - R - 0.5f)) + 1;
+}
+
+__device__ __forceinline__ uint32_t gauss_tile_of(float2 r, const GaussParams &gp) {
+  const int i0 = max(first_tap(r.x, gp.R), 0);
+  const int j0 = max(first_tap(r.y, gp.R), 0);
+  return static_cast<uint32_t>((j0 >> kGTileLog) * gp.tiles_x + (i0 >> kGTileLog));
+}
+
+__device__ uint32_t gblock_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t i0 = 2u * tid, i1 = i0 + 1u;
+  const uint32_t v0 = i0 < n ? a[i0] : 0u;
+  const uint32_t v1 = i1 < n ? a[i1] : 0u;
+  const uint32_t s = v0 + v1;
+  uint32_t incl = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t x = lane < kGWaves ? wsum[lane] : 0u;
+    uint32_t xi = x;
+#pragma unroll
+    for (int d = 1; d < kGWaves; d <<= 1) {
+      const uint32_t y = __shfl_up(xi, d, 64);
+      if (lane >= d) xi += y;
+    }
+    if (lane < kGWaves) wsum[lane] = xi - x;
+    if (lane == kGWaves - 1) wsum[kGWaves] = xi;
+  }
+  __syncthreads();
+  const uint32_t excl = wsum[w] + incl - s;
+  if (i0 < n) a[i0] = excl;
+  if (i1 < n) a[i1] = excl + v0;
+  const uint32_t total = wsum[kGWaves];
+  __syncthreads();
+  return total;
+}
+
+__device__ void gauss_flush(float2 *stage, uint32_t *cnt, uint32_t *wsum, int used, uint32_t chunk,
+                            const GaussParams &gp, const GaussBin &gb) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  float2 e[kGSlots];
+  uint32_t tl[kGSlots], r[kGSlots];
+#pragma unroll
+  for (int i = 0; i < kGSlots; ++i) {
+    e[i] = i < used ? stage[i * kGBlock + tid] : make_float2(__uint_as_float(kGInvalid), 0.f);
+    tl[i] = rec_valid(e[i]) ? gauss_tile_of(e[i], gp) : kGInvalid;
+    r[i] = tl[i] != kGInvalid ? atomicAdd(&cnt[tl[i]], 1u) : 0u;
+  }
+  __syncthreads();  // every count complete before the scan reads them
+  const uint32_t total = gblock_exclusive_scan(cnt, gb.n_tiles, wsum);
+  const uint32_t base = chunk * kGCap;
+  for (uint32_t t = tid; t <= gb.n_tiles; t += kGBlock)
+    gb.tile_start[static_cast<size_t>(t) * gb.n_chunks + chunk] =
+        base + (t < gb.n_tiles ? cnt[t] : total);
+#pragma unroll
+  for (int i = 0; i < kGSlots; ++i)
+    if (tl[i] != kGInvalid) stage[cnt[tl[i]] + r[i]] = e[i];
+  __syncthreads();
+  for (uint32_t i = tid; i < total; i += kGBlock) gb.records[static_cast<size_t>(base) + i] = stage[i];
+  __syncthreads();
+  for (uint32_t t = tid; t < gb.n_tiles; t += kGBlock) cnt[t] = 0u;
+  __syncthreads();
+}
+
+template <bool EQUAL>
+__global__ __launch_bounds__(kGBlock) void k_splat_emit(MapTable<2> mt, RunArgs ra, GaussParams gp,
+                                                        GaussBin gb, GaussCkpt ck,
+                                                        unsigned long long *dropped_out) {
+  __shared__ float table[kMaxMaps * 8];
+  __shared__ uint32_t th[kMaxMaps];
+  __shared__ float2 stage[kGCap];
+  __shared__ uint32_t cnt[kGMaxTiles];
+  __shared__ uint32_t wsum[kGWaves + 1];
+  const int tid = threadIdx.x;
+  load_table<float, 2>(mt, table, th);
+  for (uint32_t t = tid; t < gb.n_tiles; t += kGBlock) cnt[t] = 0u;
+  __syncthreads();
+
+  const uint32_t n = blockIdx.x * kGBlock + tid;
+  const bool active = n < ra.n_points;
+  const uint32_t pid = ra.point_offset + (active ? n : 0u);
+  const uint32_t T = ra.n_iters, B = ra.burn_in;
+  float p[2];
+  initial_point<float, 2>(pid, ra.instance, ra.k0, ra.k1, p);
+  if (active && ck.ckpt) reinterpret_cast<float2 *>(ck.ckpt)[n] = make_float2(p[0], p[1]);
+  uint32_t dropped = 0;
+  int slot = 0;
+  uint32_t chunk = blockIdx.x * gb.flushes;
+  const float lim = gp.R + 16.0f;
+
+  for (uint32_t t0 = 0; t0 < T; t0 += 4) {
+    const Block4 blk = philox10(pid, t0 >> 2, ra.instance, 0u, ra.k0, ra.k1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t = t0 + j + 1;
+      if (t > T) break;
+      const uint32_t u = word_of(blk, j);
+      int k;
+      if constexpr (EQUAL)
+        k = select_equal(u, static_cast<uint32_t>(mt.n_maps));
+      else
+        k = select_table(u, th, mt.n_search, mt.top_step);
+      apply_map<float, 2>(table, k, p);
+      if (active && ck.ckpt && t < T && t % ck.every == 0)
+        reinterpret_cast<float2 *>(ck.ckpt)[static_cast<size_t>(t / ck.every) * ck.stride + n] =
+            make_float2(p[0], p[1]);
+      if (t > B) {
+        float2 rec = make_float2(__uint_as_float(kGInvalid), 0.f);
+        if (active) {
+          const float x = (p[0] - gp.lo[0]) * gp.scale[0];
+          const float y = (p[1] - gp.lo[1]) * gp.scale[1];
+          if (x > -lim && x < gp.width + lim && y > -lim && y < gp.height + lim) {
+            const int i0 = first_tap(x, gp.R), j0 = first_tap(y, gp.R);
+            if (i0 + gp.taps - 1 >= 0 && i0 <= gp.width - 1 && j0 + gp.taps - 1 >= 0 &&
+                j0 <= gp.height - 1)
+              rec = make_float2(x, y);
+          }
+          if (!rec_valid(rec)) ++dropped;
+        }
+        stage[slot * kGBlock + tid] = rec;
+        if (++slot == kGSlots) {
+          gauss_flush(stage, cnt, wsum, slot, chunk, gp, gb);
+          slot = 0;
+          ++chunk;
+        }
+      }
+    }
+  }
+  if (slot > 0) gauss_flush(stage, cnt, wsum, slot, chunk, gp, gb);
+  if (active && dropped_out && dropped)
+    __hip_atomic_fetch_add(dropped_out, static_cast<unsigned long long>(dropped), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tap weights g(i + 0.5 - x) for the TAPS candidate taps from i0; taps outside
+// [lo, hi) (tile and image bounds) get weight 0.
+template <int TAPS>
+__device__ __forceinline__ void tap_weights(float x, int i0, int lo, int hi, const GaussParams &gp,
+                                            float g[TAPS]) {
+#pragma unroll
+  for (int a = 0; a < TAPS; ++a) {
+    const int i = i0 + a;
+    const float d = static_cast<float>(i) + 0.5f - x;
+    const float e = __expf(-d * d * gp.inv2s2) - gp.cutoff;
+    g[a] = (i >= lo && i < hi && fabsf(d) < gp.R) ? e : 0.0f;
+  }
+}
+
+template <int TAPS>
+__global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *__restrict__ rec,
+                                                                 const uint32_t *__restrict__ tile_start,
+                                                                 uint32_t n_chunks, GaussParams gp,
+                                                                 float *__restrict__ dens) {
+  __shared__ float acc[kGTile * kGTile];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tx = blockIdx.x % gp.tiles_x, ty = blockIdx.x / gp.tiles_x;
+  const int x0 = tx * kGTile, y0 = ty * kGTile;
+  const int xlo = x0, xhi = min(x0 + kGTile, gp.width);
+  const int ylo = y0, yhi = min(y0 + kGTile, gp.height);
+  for (int i = tid; i < kGTile * kGTile; i += kGAccBlock) acc[i] = 0.0f;
+  __syncthreads();
+  constexpr int kWav = kGAccBlock / 64;
+  for (int src = 0; src < 4; ++src) {
+    const int sx = tx - (src & 1), sy = ty - (src >> 1);
+    if (sx < 0 || sy < 0) continue;
+    const uint32_t st = static_cast<uint32_t>(sy * gp.tiles_x + sx);
+    const uint32_t *row0 = tile_start + static_cast<size_t>(st) * n_chunks;
+    const uint32_t *row1 = row0 + n_chunks;
+    for (uint32_t cb = static_cast<uint32_t>(w) * 64u; cb < n_chunks; cb += kWav * 64u) {
+      const uint32_t c = cb + lane;
+      const uint32_t s = c < n_chunks ? row0[c] : 0u;
+      const uint32_t e = c < n_chunks ? row1[c] : 0u;
+      for (int j = 0; j < 64; ++j) {
+        const uint32_t sj = __builtin_amdgcn_readlane(s, j);
+        const uint32_t ej = __builtin_amdgcn_readlane(e, j);
+        for (uint32_t i = sj + lane; i < ej; i += 64) {
+          const float2 r = rec[i];
+          const int i0 = first_tap(r.x, gp.R), j0 = first_tap(r.y, gp.R);
+          if (i0 >= xhi || i0 + TAPS <= xlo || j0 >= yhi || j0 + TAPS <= ylo) continue;
+          float gx[TAPS], gy[TAPS];
+          tap_weights<TAPS>(r.x, i0, xlo, xhi, gp, gx);
+          tap_weights<TAPS>(r.y, j0, ylo, yhi, gp, gy);
+#pragma unroll
+          for (int b = 0; b < TAPS; ++b) {
+            if (gy[b] == 0.0f) continue;
+            const float wy = gy[b] * gp.weight;
+#pragma unroll
+            for (int a = 0; a < TAPS; ++a)
+              if (gx[a] != 0.0f)
+                atomicAdd(&acc[(j0 + b - y0) * kGTile + (i0 + a - x0)], gx[a] * wy);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < kGTile * kGTile; i += kGAccBlock) {
+    const int px = x0 + (i & (kGTile - 1)), py = y0 + (i >> kGTileLog);
+    const float v = acc[i];
+    if (px < gp.width && py < gp.height && v != 0.0f) dens[static_cast<size_t>(py) * gp.width + px] += v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward
+// ---------------------------------------------------------------------------
+template <int TAPS>
+__device__ __forceinline__ void splat_grad(float px, float py, const GaussParams &gp,
+                                           const float *__restrict__ G, float *sx, float *sy) {
+  *sx = 0.0f;
+  *sy = 0.0f;
+  const float x = (px - gp.lo[0]) * gp.scale[0];
+  const float y = (py - gp.lo[1]) * gp.scale[1];
+  const float lim = gp.R + 16.0f;
+  if (!(x > -lim && x < gp.width + lim && y > -lim && y < gp.height + lim)) return;
+  const int i0 = first_tap(x, gp.R), j0 = first_tap(y, gp.R);
+  float gx[TAPS], dgx[TAPS], gy[TAPS], dgy[TAPS];
+#pragma unroll
+  for (int a = 0; a < TAPS; ++a) {
+    const int i = i0 + a;
+    const float d = static_cast<float>(i) + 0.5f - x;
+    const float e = __expf(-d * d * gp.inv2s2);
+    const bool on = i >= 0 && i < gp.width && fabsf(d) < gp.R;
+    gx[a] = on ? e - gp.cutoff : 0.0f;
+    dgx[a] = on ? -d * gp.inv_s2 * e : 0.0f;
+    const int jj = j0 + a;
+    const float dy = static_cast<float>(jj) + 0.5f - y;
+    const float ey = __expf(-dy * dy * gp.inv2s2);
+    const bool ony = jj >= 0 && jj < gp.height && fabsf(dy) < gp.R;
+    gy[a] = ony ? ey - gp.cutoff : 0.0f;
+    dgy[a] = ony ? -dy * gp.inv_s2 * ey : 0.0f;
+  }
+  float ax = 0.0f, ay = 0.0f;
+#pragma unroll
+  for (int b = 0; b < TAPS; ++b) {
+    if (gy[b] == 0.0f && dgy[b] == 0.0f) continue;
+    const float *row = G + static_cast<size_t>(j0 + b) * gp.width;
+    float sg = 0.0f, sdg = 0.0f;
+#pragma unroll
+    for (int a = 0; a < TAPS; ++a) {
+      if (gx[a] == 0.0f && dgx[a] == 0.0f) continue;
+      const float v = row[i0 + a];
+      sg += v * gx[a];
+      sdg += v * dgx[a];
+    }
+    ax += gy[b] * sdg;
+    ay += dgy[b] * sg;
+  }
+  // d(dx)/dp_x = -scale_x, d(dy)/dp_y = -scale_y
+  *sx = -ax * gp.scale[0] * gp.weight;
+  *sy = -ay * gp.scale[1] * gp.weight;
+}
+
+template <int TAPS, int NG, bool EQUAL>
+__global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, RunArgs ra,
+                                                               GaussParams gp,
+                                                               const float *__restrict__ dLdD,
+                                                               GaussCkpt ck, float *partials) {
+  __shared__ float table[kMaxMaps * 8];
+  __shared__ uint32_t th[kMaxMaps];
+  __shared__ float red[kGBwdBlock / 64][NG * 6];
+  load_table<float, 2>(mt, table, th);
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t n = blockIdx.x * kGBwdBlock + tid;
+  const bool active = n < ra.n_points;
+  const uint32_t pid = ra.point_offset + (active ? n : 0u);
+  const uint32_t T = ra.n_iters, B = ra.burn_in;
+  const uint32_t c = static_cast<uint32_t>(ck.every);
+  float g[NG][6];
+#pragma unroll
+  for (int m = 0; m < NG; ++m)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) g[m][q] = 0.0f;
+
+  if (active) {
+    float lam0 = 0.0f, lam1 = 0.0f;
+    int k_next = -1;
+    const uint32_t n_seg = (T + c - 1) / c;
+    for (int seg = static_cast<int>(n_seg) - 1; seg >= 0; --seg) {
+      const uint32_t t_start = static_cast<uint32_t>(seg) * c;
+      const uint32_t len = min(c, T - t_start);
+      float px[kMaxSeg + 1], py[kMaxSeg + 1];
+      int ks[kMaxSeg + 1];
+      const float2 p0 = reinterpret_cast<const float2 *>(ck.ckpt)[static_cast<size_t>(seg) * ck.stride + n];
+      px[0] = p0.x;
+      py[0] = p0.y;
+      ks[0] = 0;
+      // recompute the segment exactly as the forward pass did
+      Block4 blk{0u, 0u, 0u, 0u};
+      float p[2] = {p0.x, p0.y};
+#pragma unroll
+      for (int m = 1; m <= kMaxSeg; ++m) {
+        if (static_cast<uint32_t>(m) > len) break;
+        const uint32_t t = t_start + m;
+        if (m == 1 || ((t - 1) & 3u) == 0u)
+          blk = philox10(pid, (t - 1) >> 2, ra.instance, 0u, ra.k0, ra.k1);
+        const uint32_t u = word_of(blk, static_cast<int>((t - 1) & 3u));
+        int k;
+        if constexpr (EQUAL)
+          k = select_equal(u, static_cast<uint32_t>(mt.n_maps));
+        else
+          k = select_table(u, th, mt.n_search, mt.top_step);
+        apply_map<float, 2>(table, k, p);
+        px[m] = p[0];
+        py[m] = p[1];
+        ks[m] = k;
+      }
+      // reverse sweep
+#pragma unroll
+      for (int m = kMaxSeg; m >= 1; --m) {
+        if (static_cast<uint32_t>(m) > len) continue;
+        const uint32_t t = t_start + m;
+        float s0 = 0.0f, s1 = 0.0f;
+        if (t > B) splat_grad<TAPS>(px[m], py[m], gp, dLdD, &s0, &s1);
+        float c0 = 0.0f, c1 = 0.0f;
+        if (k_next >= 0) {
+          const float *A = table + k_next * 8;  // a00 a01 a10 a11: A^T lam
+          c0 = A[0] * lam0 + A[2] * lam1;
+          c1 = A[1] * lam0 + A[3] * lam1;
+        }
+        lam0 = s0 + c0;
+        lam1 = s1 + c1;
+        const int k = ks[m];
+        const float q0 = px[m - 1], q1 = py[m - 1];
+#pragma unroll
+        for (int mm = 0; mm < NG; ++mm) {
+          const float sel = (k == mm) ? 1.0f : 0.0f;
+          const float l0 = sel * lam0, l1 = sel * lam1;
+          g[mm][0] += l0 * q0;
+          g[mm][1] += l0 * q1;
+          g[mm][2] += l1 * q0;
+          g[mm][3] += l1 * q1;
+          g[mm][4] += l0;
+          g[mm][5] += l1;
+        }
+        k_next = k;
+      }
+    }
+  }
+  // fixed-order reduction: butterfly within the wave, then waves in order
+#pragma unroll
+  for (int m = 0; m < NG; ++m)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      float v = g[m][q];
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+      if (lane == 0) red[w][m * 6 + q] = v;
+    }
+  __syncthreads();
+  if (tid < NG * 6) {
+    float s = 0.0f;
+    for (int ww = 0; ww < kGBwdBlock / 64; ++ww) s += red[ww][tid];
+    partials[static_cast<size_t>(blockIdx.x) * (NG * 6) + tid] = s;
+  }
+}
+
+// grad[i] = sum over workgroups b in order of partials[b][i] (FP64 sum).
+__global__ void k_grad_reduce(const float *partials, uint32_t blocks, int ng6, int n6, float *grad) {
+  const int i = threadIdx.x;
+  if (i >= n6) return;
+  double s = 0.0;
+  for (uint32_t b = 0; b < blocks; ++b) s += static_cast<double>(partials[static_cast<size_t>(b) * ng6 + i]);
+  grad[i] = static_cast<float>(s);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+GaussPlan gauss_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, int width, int height) {
+  GaussPlan gp{};
+  gp.blocks = (points + kGBlock - 1) / kGBlock;
+  gp.flushes = (n_iters - burn_in + kGSlots - 1) / kGSlots;
+  gp.n_chunks = gp.blocks * gp.flushes;
+  gp.tiles_x = (width + kGTile - 1) / kGTile;
+  gp.tiles_y = (height + kGTile - 1) / kGTile;
+  gp.n_tiles = static_cast<uint32_t>(gp.tiles_x) * gp.tiles_y;
+  gp.records_bytes = static_cast<size_t>(gp.n_chunks) * kGCap * sizeof(float2);
+  gp.table_bytes = static_cast<size_t>(gp.n_tiles + 1) * gp.n_chunks * sizeof(uint32_t);
+  return gp;
+}
+
+hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
+  if (j.ra.n_points == 0 || j.gb.n_chunks == 0) return hipSuccess;
+  const uint32_t blocks = (j.ra.n_points + kGBlock - 1) / kGBlock;
+  if (j.equal)
+    hipLaunchKernelGGL(k_splat_emit<true>, dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp, j.gb,
+                       j.ck, j.dropped);
+  else
+    hipLaunchKernelGGL(k_splat_emit<false>, dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp, j.gb,
+                       j.ck, j.dropped);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (j.gp.taps <= 6)
+    hipLaunchKernelGGL(k_splat_accumulate<6>, dim3(j.gb.n_tiles), dim3(kGAccBlock), 0, s,
+                       j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, j.dens);
+  else
+    hipLaunchKernelGGL(k_splat_accumulate<16>, dim3(j.gb.n_tiles), dim3(kGAccBlock), 0, s,
+                       j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, j.dens);
+  return hipGetLastError();
+}
+
+template <int TAPS, int NG>
+static void launch_bwd_typed(const GaussJob &j, uint32_t blocks, hipStream_t s) {
+  if (j.equal)
+    hipLaunchKernelGGL((k_splat_backward<TAPS, NG, true>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt,
+                       j.ra, j.gp, j.dLdD, j.ck, j.partials);
+  else
+    hipLaunchKernelGGL((k_splat_backward<TAPS, NG, false>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt,
+                       j.ra, j.gp, j.dLdD, j.ck, j.partials);
+}
+
+hipError_t launch_splat_backward(const GaussJob &j, hipStream_t s) {
+  const uint32_t blocks = (j.ra.n_points + kGBwdBlock - 1) / kGBwdBlock;
+  const int ng = j.mt.n_maps <= 4 ? 4 : 8;
+  if (blocks > 0) {
+    if (j.gp.taps <= 6) {
+      if (ng == 4) launch_bwd_typed<6, 4>(j, blocks, s); else launch_bwd_typed<6, 8>(j, blocks, s);
+    } else {
+      if (ng == 4) launch_bwd_typed<16, 4>(j, blocks, s); else launch_bwd_typed<16, 8>(j, blocks, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(64), 0, s, j.partials, blocks, ng * 6,
+                     j.mt.n_maps * 6, j.grad);
+  return hipGetLastError();
+}
+
+}  // namespace cfs
