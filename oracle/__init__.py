@@ -9,11 +9,12 @@ contraction); this module only builds it with gcc and marshals numpy arrays.
 Every function cites the part of the paper it follows in the C source.
 
 Parity status:
-  philox4x32_10      pinned: known-answer vectors, rocRAND host generator
+  philox4x32_10      pinned: published known-answer vectors
   thresholds/select  pinned: exhaustive over all 2^32 draws, closed form
   chaos_count        pinned: invariant-measure moments, uniform square,
                      Sierpinski box dimension, address containment,
-                     composition order
+                     composition order; circle maps: invariant uniform disk
+                     (moments of r^2, half-disk per index)
   chaos_depth        pinned: Menger occupancy of the 3^k grid and box
                      dimension for the 3D points; the projected depth image
                      itself is parity unpinned beyond the oracle
@@ -34,6 +35,8 @@ _SRC = os.path.join(_HERE, "cfs_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_cfs_oracle.so")
 
 FINAL_KINDS = {"identity": 0, "swirl": 1, "twist_camera": 2, "stretch": 3}
+MAP_KINDS = {"affine": 0, "circle": 1}
+COMPOSE = {"copy": 0, "reuse": 1}
 
 
 def build(force: bool = True) -> str:
@@ -51,7 +54,8 @@ class _System(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_maps", C.c_int32),
                 ("A", C.POINTER(C.c_float)), ("b", C.POINTER(C.c_float)),
                 ("prob", C.POINTER(C.c_double)), ("final_kind", C.c_int32),
-                ("final_params", C.POINTER(C.c_float))]
+                ("final_params", C.POINTER(C.c_float)), ("kind", C.POINTER(C.c_int32)),
+                ("compose", C.c_int32)]
 
 
 class _Run(C.Structure):
@@ -107,12 +111,18 @@ class _Keep:
         src = np.asarray(system.get("final_params", []), np.float32).reshape(-1)
         fp[: src.size] = src
         self.fp = fp
+        kinds = system.get("kind")
+        self.kind = None if kinds is None else np.ascontiguousarray(
+            [MAP_KINDS[k] if isinstance(k, str) else int(k) for k in kinds], dtype=np.int32)
         self.s = _System(d, n, self.A.ctypes.data_as(C.POINTER(C.c_float)),
                          self.b.ctypes.data_as(C.POINTER(C.c_float)),
                          None if self.prob is None else
                          self.prob.ctypes.data_as(C.POINTER(C.c_double)),
                          FINAL_KINDS[system.get("final_kind", "identity")],
-                         self.fp.ctypes.data_as(C.POINTER(C.c_float)))
+                         self.fp.ctypes.data_as(C.POINTER(C.c_float)),
+                         None if self.kind is None else
+                         self.kind.ctypes.data_as(C.POINTER(C.c_int32)),
+                         COMPOSE[system.get("compose", "copy")])
 
 
 def _run(run):

@@ -46,6 +46,10 @@
 #define ORC_FINAL_STRETCH 3
 
 #define ORC_MAX_MAPS 64
+
+/* Map kinds. */
+#define ORC_MAP_AFFINE 0
+#define ORC_MAP_CIRCLE 1
 #define ORC_MAX_DIM 3
 
 /* ------------------------------------------------------------------------ */
@@ -55,7 +59,7 @@
 /* fixed 32-bit constants to 64-bit products; the high halves are xored     */
 /* with the other two counter words and the two key words, the low halves    */
 /* move over, and the key advances by two Weyl constants between rounds.    */
-/* Pinned by known-answer vectors and by rocRAND's host Philox (run only).   */
+/* Pinned by the published known-answer vectors.                           */
 /* ------------------------------------------------------------------------ */
 static const uint32_t PHILOX_MUL0 = 0xD2511F53u;
 static const uint32_t PHILOX_MUL1 = 0xCD9E8D57u;
@@ -148,6 +152,8 @@ typedef struct {
   const double *prob;    /* [n_maps] or NULL for equal probabilities */
   int32_t final_kind;    /* ORC_FINAL_* */
   const float *final_params; /* up to 24 values, meaning per kind */
+  const int32_t *kind;   /* [n_maps] ORC_MAP_* or NULL (all affine) */
+  int32_t compose;       /* 0: transform a copy; 1: feed the transformed point back */
 } orc_system;
 
 typedef struct {
@@ -184,10 +190,31 @@ static void initial_point(const orc_run *r, uint32_t pid, int dim, double p[3]) 
   for (int c = 0; c < dim; ++c) p[c] = ldexp((double)(w[c] >> 8), -24);
 }
 
+/* Circle map (Section 3, the circle equation; 2D).  Reading of the garbled
+ * equation: with u = x^2 + y^2 (= r^2) and v = theta / (2 pi), theta the
+ * polar angle in [0, 2 pi), the new point has radius sqrt(v) and angle
+ * pi (u + f), where f is the map's id (0 or 1; taken from b_k[0]).  The map
+ * sends (u, v) to (v, (u + f) / 2), so it keeps the uniform measure of the
+ * unit disk and sends the disk onto its upper (f = 0) or lower (f = 1) half. */
+static void circle_map(double f, double p[3]) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double u = p[0] * p[0] + p[1] * p[1];
+  double th = atan2(p[1], p[0]);
+  if (th < 0.0) th += two_pi;
+  double r2 = sqrt(th / two_pi);
+  double th2 = 0.5 * two_pi * (u + f);
+  p[0] = r2 * cos(th2);
+  p[1] = r2 * sin(th2);
+}
+
 /* Apply map k: p <- A_k p + b_k (Section 3: each function maps P_n to P_{n+1};
- * the configured systems are affine). */
+ * the configured systems are affine), or the circle map for circle kinds. */
 static void apply_map(const orc_system *s, int k, double p[3]) {
   int d = s->dim;
+  if (s->kind && s->kind[k] == ORC_MAP_CIRCLE) {
+    circle_map((double)s->b[k * d], p);
+    return;
+  }
   double q[3] = {0, 0, 0};
   for (int r = 0; r < d; ++r) {
     double acc = 0.0;
@@ -282,6 +309,11 @@ static int check_common(const orc_system *s, const orc_run *r, const orc_window 
   if (!s || !r || !w) return ORC_EINVAL;
   if (s->dim < 2 || s->dim > 3) return ORC_EINVAL;
   if (s->n_maps < 1 || s->n_maps > ORC_MAX_MAPS) return ORC_EINVAL;
+  if (s->kind)
+    for (int i = 0; i < s->n_maps; ++i) {
+      if (s->kind[i] != ORC_MAP_AFFINE && s->kind[i] != ORC_MAP_CIRCLE) return ORC_EINVAL;
+      if (s->kind[i] == ORC_MAP_CIRCLE && s->dim != 2) return ORC_EINVAL;
+    }
   if (r->burn_in > r->n_iters) return ORC_EINVAL;
   if (w->width < 1 || w->height < 1 || w->channels < 1) return ORC_EINVAL;
   if (!(w->hi[0] > w->lo[0]) || !(w->hi[1] > w->lo[1])) return ORC_EINVAL;
@@ -306,6 +338,8 @@ int orc_chaos_count(const orc_system *s, const orc_run *r, const orc_window *w,
   if (rc) return rc;
   if (w->channels != 1 && w->channels != s->n_maps) return ORC_EINVAL;
   if (s->final_kind == ORC_FINAL_TWIST_CAMERA) return ORC_EINVAL;
+  if (s->compose != 0 && s->compose != 1) return ORC_EINVAL;
+  if (s->compose && s->dim != 2) return ORC_EINVAL;
   const int d = s->dim;
   const uint32_t T = r->n_iters, B = r->burn_in;
   const size_t plane = (size_t)w->width * (size_t)w->height;
@@ -322,10 +356,22 @@ int orc_chaos_count(const orc_system *s, const orc_run *r, const orc_window *w,
       k = orc_select(u, thresh, s->n_maps);
       if (idx) idx[(size_t)n * T + (t - 1)] = (uint8_t)k;
       apply_map(s, k, p);
+      if (s->compose) {
+        /* reuse (fig. "circle" C): the transformed point is the new point */
+        double q0[2], d0 = 0.0;
+        final_transform(s, p, q0, &d0);
+        p[0] = q0[0];
+        p[1] = q0[1];
+      }
       if (t > B) {
         double q[2], depth = 0.0, fx, fy;
         int ix, iy;
-        final_transform(s, p, q, &depth);
+        if (s->compose) {
+          q[0] = p[0];
+          q[1] = p[1];
+        } else {
+          final_transform(s, p, q, &depth);
+        }
         int hit = bin_point(w, q, &ix, &iy, &fx, &fy);
         if (splat_xy) {
           size_t o = ((size_t)n * (T - B) + (t - B - 1)) * 2;
@@ -362,7 +408,7 @@ int orc_chaos_depth(const orc_system *s, const orc_run *r, const orc_window *w,
   uint64_t thresh[ORC_MAX_MAPS];
   int rc = check_common(s, r, w, thresh);
   if (rc) return rc;
-  if (s->dim != 3 || s->final_kind != ORC_FINAL_TWIST_CAMERA) return ORC_EINVAL;
+  if (s->dim != 3 || s->final_kind != ORC_FINAL_TWIST_CAMERA || s->compose) return ORC_EINVAL;
   const uint32_t T = r->n_iters, B = r->burn_in;
   uint64_t n_drop = 0;
   for (uint32_t n = 0; n < r->n_points; ++n) {
@@ -464,7 +510,7 @@ int orc_splat_gauss(const orc_system *s, const orc_run *r, const orc_window *w,
   uint64_t thresh[ORC_MAX_MAPS];
   int rc = check_common(s, r, w, thresh);
   if (rc) return rc;
-  if (s->dim != 2 || s->final_kind != ORC_FINAL_IDENTITY || !(sigma > 0.0))
+  if (s->dim != 2 || s->final_kind != ORC_FINAL_IDENTITY || !(sigma > 0.0) || s->kind)
     return ORC_EINVAL;
   const uint32_t T = r->n_iters, B = r->burn_in;
   if (T == B || r->n_points == 0) return ORC_OK;
@@ -503,7 +549,7 @@ int orc_splat_gauss_backward(const orc_system *s, const orc_run *r,
   uint64_t thresh[ORC_MAX_MAPS];
   int rc = check_common(s, r, w, thresh);
   if (rc) return rc;
-  if (s->dim != 2 || s->final_kind != ORC_FINAL_IDENTITY || !(sigma > 0.0))
+  if (s->dim != 2 || s->final_kind != ORC_FINAL_IDENTITY || !(sigma > 0.0) || s->kind)
     return ORC_EINVAL;
   const int n_par = 6;
   for (int i = 0; i < s->n_maps * n_par; ++i) grad[i] = 0.0;
