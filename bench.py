@@ -29,23 +29,44 @@ VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9  # 3.93e13 lane-ops/s (full-rate ops)
 HBM_PEAK_GBS = 8000.0
 
 
-def valu_model(dim, final_kind, precision, n_points, n_iters, burn_in):
-    """Algorithmic full-rate-equivalent lane-ops of the chaos game.
+# Algorithmic VALU work per unit (full-rate-equivalent lane operations): a
+# point-iteration is a quarter of a Philox4x32-10 block (10 rounds of two
+# quarter-rate 32x32->64 multiplies and two xors: 25), the selection (4), the
+# 2D map (4 FMA) and loop control (3) = 36; a splat adds binning and address
+# (10) and, for the swirl, its square root and sine/cosine (20).  FP64
+# transcendentals cost more than this counts, so the fraction is conservative.
+PER_POINT_ITERATION = 36
+PER_SPLAT = {"identity": 10, "swirl": 30, "stretch": 25}
 
-    Per point-iteration: a quarter of a Philox4x32-10 block (10 rounds x
-    (2 quarter-rate 32x32->64 multiplies + 2 xors) = 100 per block), one
-    quarter-rate mul_hi for the selection, d*d FMAs for the map, one for the
-    loop.  Per point: one more Philox block for the initial point and d
-    conversions.  Per splat: the composed transform, the binning and the
-    atomic's address (constants per kind below)."""
-    per_it = 25 + 4 + dim * dim + 1
-    per_point = 100 + 2 * dim
-    splat_cost = {("identity", "f32"): 12, ("identity", "f64"): 12,
-                  ("swirl", "f32"): 12 + 30, ("swirl", "f64"): 12 + 45,
-                  ("stretch", "f32"): 12 + 20, ("stretch", "f64"): 12 + 30}
-    per_splat = splat_cost.get((final_kind, precision), 40)
+
+def valu_model(final_kind, n_points, n_iters, burn_in):
     splats = n_points * (n_iters - burn_in)
-    return n_points * n_iters * per_it + n_points * per_point + splats * per_splat
+    return n_points * n_iters * PER_POINT_ITERATION + splats * PER_SPLAT[final_kind]
+
+
+def source_digest():
+    """Digest of the HIP sources; traffic counters are valid only for it."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_02226_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision):
+    """HBM bytes per launch of the binned chaos kernels from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, or None when the sources changed
+    since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_cfs_square_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_digest") != source_digest():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(w, n_sample):
@@ -61,6 +82,90 @@ def cpu_baseline(w, n_sample):
                       f"full image), single-threaded FP64, {dt:.1f} s"}
 
 
+def _timed(fn, reps, stream):
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def forms(dev, precision):
+    """The batched and differentiable forms next to the plain chaos game."""
+    import torch
+    import workloads
+    from paper_2606_02226_amd import api
+    stream = torch.cuda.current_stream()
+    out = {}
+    # batched: 256 heterogeneous systems in one graph launch vs 256 plain calls
+    entries = workloads.batched()
+    images = [api.Image(w["image"], device=dev) for w in entries]
+    batch = api.Batch(entries, images, precision=precision)
+    graph_ms = _timed(batch.run, 5, stream)
+    ws = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    systems = [api.System(w["system"]) for w in entries]
+
+    def sequential():
+        for w, s_, img in zip(entries, systems, images):
+            img.clear()
+            api.chaos_game(s_, w["run"], img, precision=precision, workspace=ws)
+
+    seq_ms = _timed(sequential, 3, stream)
+    pt_its = sum(w["run"]["n_points"] * w["run"]["n_iters"] for w in entries)
+    splats = sum(w["run"]["n_points"] * (w["run"]["n_iters"] - w["run"]["burn_in"]) for w in entries)
+    out["batched"] = {
+        "workload": "256 random affine systems, 2..16 maps, 2^12..2^20 points x 32 "
+                    "iterations (8 burn-in), 256^2..1024^2 u32 images",
+        "precision": precision, "point_iterations": pt_its, "graph_ms": graph_ms,
+        "point_iterations_per_s": pt_its / (graph_ms * 1e-3),
+        "splats_per_s": splats / (graph_ms * 1e-3),
+        "sequential_plain_ms": seq_ms, "speedup_vs_sequential_plain": seq_ms / graph_ms,
+        "plan": batch.plan(), "error": "each instance bit-identical to its plain run"}
+    batch.close()
+    del images, ws
+    # differentiable: forward + adjoint vs the plain count chaos game, same N, T
+    w = workloads.differentiable()
+    N, T = w["run"]["n_points"], w["run"]["n_iters"]
+    img = api.Image(w["image"], device=dev)
+    every = w["ckpt_every"]
+    ckpt = torch.empty((api.n_checkpoints(T, every), N, 2), dtype=torch.float32, device=dev)
+    G = torch.randn((512, 512), dtype=torch.float32, device=dev)
+    sys_d = api.System(w["system"])
+
+    def fwd():
+        img.clear()
+        api.splat(sys_d, w["run"], img, w["sigma_px"], ckpt=ckpt, ckpt_every=every)
+
+    def bwd():
+        api.splat_backward(sys_d, w["run"], img, w["sigma_px"], G, ckpt, every)
+
+    fwd_ms = _timed(fwd, 10, stream)
+    bwd_ms = _timed(bwd, 10, stream)
+    cimg = api.Image({"kind": "u32_count", "width": 512, "height": 512, "channels": 1,
+                      "lo": [0, 0], "hi": [1, 1]}, device=dev)
+
+    def plain():
+        cimg.clear()
+        api.chaos_game(sys_d, w["run"], cimg, precision="f32")
+
+    plain_ms = _timed(plain, 10, stream)
+    out["grad"] = {
+        "workload": "4-map affine system, 2^20 points x 32 iterations (8 burn-in), "
+                    "Gaussian splat sigma 1 px into 512x512 FP32, checkpoints every 8",
+        "forward_ms": fwd_ms, "backward_ms": bwd_ms, "forward_backward_ms": fwd_ms + bwd_ms,
+        "plain_count_ms": plain_ms, "ratio_vs_plain": (fwd_ms + bwd_ms) / plain_ms,
+        "checkpoint_bytes": int(ckpt.numel() * 4),
+        "full_trajectory_bytes": int(N * (T + 1) * 2 * 4),
+        "error": "gradient within 1e-4 rel. L2 of the FP64 adjoint and 1e-3 of FD (tests)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +176,9 @@ def main():
     ap.add_argument("--splat-path", choices=["auto", "direct", "binned"], default="auto")
     ap.add_argument("--cpu-sample-log2", type=int, default=21)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="copy 256 MiB once before timing (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
@@ -104,6 +212,12 @@ def main():
         if ev is not None:
             ev[1].record(stream)
 
+    if args.calibration_copy:
+        src = torch.empty(64 << 20, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -125,7 +239,7 @@ def main():
     pt_its = N * T
     splats = N * (T - B)
     value = pt_its * args.steps / elapsed
-    lane_ops = valu_model(2, "swirl", args.precision, N, T, B)
+    lane_ops = valu_model("swirl", N, T, B)
     achieved = lane_ops / (kernel_ms * 1e-3) / 1e12
     peak = VALU_LANE_OPS_PEAK / 1e12
     result = {
@@ -144,10 +258,14 @@ def main():
                    "points": N, "iterations": T, "burn_in": B,
                    "image": [4, 2048, 2048], "precision": args.precision},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
-                     "unit": "Tlane-op/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_chaos (swirl, 4-channel count)",
-                     "lane_ops_per_launch": lane_ops},
+                     "unit": "Tlane-op/s", "frac": achieved / peak,
+                     "traffic": measured_traffic(args.precision),
+                     "kernel": "k_chaos_binned + k_tile_accumulate (swirl, 4-channel count)",
+                     "lane_ops_per_launch": lane_ops,
+                     "timing": "HIP events around cfs_chaos_game on its stream"},
     }
+    if not args.no_forms:
+        result["forms"] = forms(dev, args.precision)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, 1 << args.cpu_sample_log2)
     print(json.dumps(result))

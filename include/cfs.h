@@ -94,16 +94,36 @@ enum {
 /* Arithmetic type of the point positions and transforms on the GPU. */
 enum { CFS_PREC_F32 = 0, CFS_PREC_F64 = 1 };
 
-/* How integer count splats reach the image.  DIRECT: one device atomic per
- * splat.  BINNED: each workgroup sorts its splats by image tile in LDS and
- * writes them out as per-tile runs; a second kernel accumulates every tile
- * in LDS and adds it into the image (needs workspace, images of at most
- * 2^25 elements).  AUTO picks BINNED for large runs that qualify.  Both give
- * bit-identical images. */
+/* How integer splats (counts, depth keys) reach the image.  DIRECT: device
+ * atomics per splat.  BINNED: each workgroup sorts its splats by image tile
+ * in LDS and writes them out as per-tile runs; a second kernel accumulates
+ * every tile in LDS and merges it into the image (needs workspace; count
+ * images of at most 2^25 elements, depth images of at most 2^24 pixels).
+ * AUTO picks BINNED for large runs that qualify.  Both give bit-identical
+ * images (integer sums and minima do not depend on order). */
 enum { CFS_SPLAT_AUTO = 0, CFS_SPLAT_DIRECT = 1, CFS_SPLAT_BINNED = 2 };
 
-/* A function system: n affine maps p -> A_k p + b_k and a composed transform.
- * The map table is copied into kernel arguments (a few KiB at most). */
+/* How the composed transform meets the iteration (Section 3, fig. "circle"
+ * B vs C): COPY transforms a copy of the point before the splat and keeps
+ * iterating the original; REUSE feeds the transformed point back, so the
+ * iterated maps are the transform composed with each map (2D transforms
+ * only, count images only). */
+enum { CFS_COMPOSE_COPY = 0, CFS_COMPOSE_REUSE = 1 };
+
+/* Kinds of the maps of a system. */
+enum {
+  CFS_MAP_AFFINE = 0, /* p -> A_k p + b_k */
+  CFS_MAP_CIRCLE = 1  /* 2D, the circle map of Section 3's circle equation,
+                         read as: u = |p|^2, v = (polar angle in [0, 2 pi))
+                         / (2 pi); the image has radius sqrt(v) and angle
+                         pi (u + f) with f = b_k[0] (the map's id, 0 or 1);
+                         it keeps the uniform disk and sends it onto its
+                         upper (f = 0) or lower (f = 1) half; A_k unused */
+};
+
+/* A function system: n maps (affine unless `kind` says otherwise) and a
+ * composed transform.  The map table is copied into kernel arguments (a few
+ * KiB at most). */
 typedef struct cfs_system {
   int32_t dim;            /* 2 or 3 */
   int32_t n_maps;         /* 1 .. CFS_MAX_MAPS */
@@ -112,6 +132,9 @@ typedef struct cfs_system {
   const double *prob;     /* host [n_maps] summing to 1 (+-1e-6), or NULL */
   int32_t final_kind;     /* CFS_FINAL_* */
   float final_params[24]; /* meaning per final_kind, unused entries ignored */
+  const int32_t *kind;    /* host [n_maps] CFS_MAP_*, or NULL (all affine);
+                             circle maps need dim 2 */
+  int32_t compose;        /* CFS_COMPOSE_COPY (default) or CFS_COMPOSE_REUSE */
 } cfs_system;
 
 /* One run over a range of points. */

@@ -22,6 +22,8 @@ CFS_MAX_MAPS = 64
 FINAL_KINDS = {"identity": 0, "swirl": 1, "twist_camera": 2, "stretch": 3}
 IMAGE_KINDS = {"u32_count": 0, "f32_density": 1, "u64_depth": 2}
 PRECISIONS = {"f32": 0, "f64": 1}
+MAP_KINDS = {"affine": 0, "circle": 1}
+COMPOSE = {"copy": 0, "reuse": 1}
 SPLAT_PATHS = {"auto": 0, "direct": 1, "binned": 2}
 
 # Every symbol include/cfs.h declares.
@@ -37,7 +39,8 @@ class CfsSystem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_maps", C.c_int32),
                 ("A", C.POINTER(C.c_float)), ("b", C.POINTER(C.c_float)),
                 ("prob", C.POINTER(C.c_double)), ("final_kind", C.c_int32),
-                ("final_params", C.c_float * 24)]
+                ("final_params", C.c_float * 24), ("kind", C.POINTER(C.c_int32)),
+                ("compose", C.c_int32)]
 
 
 class CfsRun(C.Structure):

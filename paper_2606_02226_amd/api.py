@@ -44,11 +44,16 @@ class System:
         src = np.asarray(system.get("final_params", []), np.float32).reshape(-1)
         for i, v in enumerate(src[:24]):
             fp[i] = float(v)
+        kinds = system.get("kind")
+        self.kind = None if kinds is None else np.ascontiguousarray(
+            [_lib.MAP_KINDS[k] if isinstance(k, str) else int(k) for k in kinds], np.int32)
         self.struct = CfsSystem(
             d, n, self.A.ctypes.data_as(C.POINTER(C.c_float)),
             self.b.ctypes.data_as(C.POINTER(C.c_float)),
             None if self.prob is None else self.prob.ctypes.data_as(C.POINTER(C.c_double)),
-            _lib.FINAL_KINDS[system.get("final_kind", "identity")], fp)
+            _lib.FINAL_KINDS[system.get("final_kind", "identity")], fp,
+            None if self.kind is None else self.kind.ctypes.data_as(C.POINTER(C.c_int32)),
+            _lib.COMPOSE[system.get("compose", "copy")])
         self.dim, self.n_maps = d, n
 
 

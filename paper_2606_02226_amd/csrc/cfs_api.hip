@@ -85,6 +85,17 @@ int validate_system(const cfs_system *s) {
       break;
     default: return fail(CFS_E_INVALID, "unknown final kind %d", s->final_kind);
   }
+  if (s->kind)
+    for (int i = 0; i < s->n_maps; ++i) {
+      if (s->kind[i] != CFS_MAP_AFFINE && s->kind[i] != CFS_MAP_CIRCLE)
+        return fail(CFS_E_INVALID, "kind[%d] = %d is not a map kind", i, s->kind[i]);
+      if (s->kind[i] == CFS_MAP_CIRCLE && d != 2)
+        return fail(CFS_E_INVALID, "circle maps need dim 2");
+    }
+  if (s->compose != CFS_COMPOSE_COPY && s->compose != CFS_COMPOSE_REUSE)
+    return fail(CFS_E_INVALID, "compose = %d is not a composition mode", s->compose);
+  if (s->compose == CFS_COMPOSE_REUSE && d != 2)
+    return fail(CFS_E_INVALID, "reuse composition needs a 2D transform (dim 2)");
   uint64_t th[CFS_MAX_MAPS];
   return make_thresholds(s->prob, s->n_maps, th);
 }
@@ -166,6 +177,15 @@ int pack_table(const cfs_system *s, MapTable<DIM> *mt, bool *equal) {
     }
   }
   mt->n_maps = n;
+  mt->flags = 0;
+  mt->circle_mask = 0;
+  if (s->kind)
+    for (int m = 0; m < n; ++m)
+      if (s->kind[m] == CFS_MAP_CIRCLE) {
+        mt->circle_mask |= 1ull << m;
+        mt->flags |= kFlagCircle;
+      }
+  if (s->compose == CFS_COMPOSE_REUSE) mt->flags |= kFlagReuse;
   uint64_t th[CFS_MAX_MAPS];
   const int rc = make_thresholds(s->prob, n, th);
   if (rc) return rc;
@@ -229,11 +249,13 @@ extern "C" int cfs_image_clear(const cfs_image *img, void *stream) {
 namespace {
 
 // Points per launch of the binned path: at most 2^24, and few enough that the
-// records of one launch take at most 1 GiB (2^29 16-bit records), which also
-// keeps record indices within 31 bits.
-uint32_t binned_slice(const cfs_run *run) {
-  const uint64_t flushes = (run->n_iters - run->burn_in + kBinSlots - 1) / kBinSlots;
-  uint64_t max_blocks = (1ull << 29) / (flushes * kChunkCap);
+// records of one launch take at most 1 GiB (2^29 16-bit or 2^27 8-byte
+// records), which also keeps record indices within 31 bits.
+uint32_t binned_slice(const cfs_run *run, bool depth) {
+  const uint64_t slots = depth ? kDSlots : kBinSlots;
+  const uint64_t cap = depth ? kDCap : kChunkCap;
+  const uint64_t flushes = (run->n_iters - run->burn_in + slots - 1) / slots;
+  uint64_t max_blocks = (depth ? (1ull << 27) : (1ull << 29)) / (flushes * cap);
   if (max_blocks < 1) max_blocks = 1;
   uint64_t pts = max_blocks * kBinBlock;
   if (pts > (1ull << 24)) pts = 1ull << 24;
@@ -243,10 +265,12 @@ uint32_t binned_slice(const cfs_run *run) {
 
 // Whether this call takes the binned splat (arguments already validated).
 bool use_binned(const cfs_run *run, const cfs_image *img) {
-  if (img->kind != CFS_IMAGE_U32_COUNT || run->splat_path == CFS_SPLAT_DIRECT) return false;
+  if (run->splat_path == CFS_SPLAT_DIRECT) return false;
+  if (img->kind != CFS_IMAGE_U32_COUNT && img->kind != CFS_IMAGE_U64_DEPTH) return false;
   if (run->n_iters == run->burn_in || run->n_points == 0) return false;
   const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
-  if (elems > static_cast<uint64_t>(kMaxTiles) * kTileElems) return false;
+  const uint64_t tile = img->kind == CFS_IMAGE_U64_DEPTH ? kDTileElems : kTileElems;
+  if (elems > static_cast<uint64_t>(kMaxTiles) * tile) return false;
   if (run->splat_path == CFS_SPLAT_BINNED) return true;
   return static_cast<uint64_t>(run->n_points) * (run->n_iters - run->burn_in) >= (1ull << 20);
 }
@@ -255,7 +279,8 @@ size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 size_t binned_workspace(const cfs_run *run, const cfs_image *img) {
   const uint32_t elems = static_cast<uint32_t>(img->width) * img->height * img->channels;
-  const BinPlan bp = bin_plan(binned_slice(run), run->n_iters, run->burn_in, elems);
+  const bool depth = img->kind == CFS_IMAGE_U64_DEPTH;
+  const BinPlan bp = bin_plan(binned_slice(run, depth), run->n_iters, run->burn_in, elems, depth);
   return align_up(bp.records_bytes) + 2 * align_up(bp.table_bytes);
 }
 
@@ -295,16 +320,15 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
       return fail(CFS_E_UNSUPPORTED, "a depth image needs the twist/camera transform");
     if (!std::isfinite(img->near_plane))
       return fail(CFS_E_INVALID, "near_plane is not finite");
-    if (run->splat_path == CFS_SPLAT_BINNED)
-      return fail(CFS_E_UNSUPPORTED, "depth images take the direct splat");
     job.depth = true;
   } else {
     return fail(CFS_E_INVALID, "cfs_chaos_game renders U32_COUNT or U64_DEPTH images");
   }
   const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
-  if (run->splat_path == CFS_SPLAT_BINNED && elems > static_cast<uint64_t>(kMaxTiles) * kTileElems)
+  const uint64_t tile = job.depth ? kDTileElems : kTileElems;
+  if (run->splat_path == CFS_SPLAT_BINNED && elems > static_cast<uint64_t>(kMaxTiles) * tile)
     return fail(CFS_E_UNSUPPORTED, "binned splat handles images of at most %u elements",
-                static_cast<unsigned>(kMaxTiles * kTileElems));
+                static_cast<unsigned>(kMaxTiles * tile));
   const size_t align = run->precision == CFS_PREC_F64 ? 8 : 4;
   if (final_points && reinterpret_cast<uintptr_t>(final_points) % align)
     return fail(CFS_E_INVALID, "final_points is not %zu-byte aligned", align);
@@ -337,11 +361,11 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
   if (!job.binned) return device_status(launch_chaos(job, s), "cfs_chaos_game");
 
   // binned: slices of at most binned_slice() points share the workspace
-  const uint32_t slice = binned_slice(run);
+  const uint32_t slice = binned_slice(run, job.depth);
   const size_t real_bytes = run->precision == CFS_PREC_F64 ? sizeof(double) : sizeof(float);
   for (uint32_t done = 0; done < run->n_points; done += slice) {
     const uint32_t pts = std::min(slice, run->n_points - done);
-    const BinPlan bp = bin_plan(pts, run->n_iters, run->burn_in, static_cast<uint32_t>(elems));
+    const BinPlan bp = bin_plan(pts, run->n_iters, run->burn_in, static_cast<uint32_t>(elems), job.depth);
     ChaosJob sj = job;
     sj.ra.n_points = pts;
     sj.ra.point_offset = run->point_offset + done;
@@ -350,6 +374,7 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
     if (last_index) sj.out.last_index = last_index + done;
     if (indices) sj.out.indices = indices + static_cast<size_t>(done) * run->n_iters;
     sj.ba.records = static_cast<uint16_t *>(workspace);
+    sj.ba.drecords = static_cast<uint2 *>(workspace);
     char *tables = static_cast<char *>(workspace) + align_up(bp.records_bytes);
     sj.ba.chunk_start = reinterpret_cast<uint32_t *>(tables);
     sj.ba.tile_start = reinterpret_cast<uint32_t *>(tables + align_up(bp.table_bytes));

@@ -22,6 +22,10 @@ int validate_gauss(const cfs_system *sys, const cfs_run *run, const cfs_image *i
   if (rc) return rc;
   if (sys->dim != 2 || sys->final_kind != CFS_FINAL_IDENTITY)
     return fail(CFS_E_UNSUPPORTED, "the Gaussian splat takes 2D systems with the identity transform");
+  if (sys->kind)
+    for (int i = 0; i < sys->n_maps; ++i)
+      if (sys->kind[i] != CFS_MAP_AFFINE)
+        return fail(CFS_E_UNSUPPORTED, "the Gaussian splat and its adjoint take affine maps only");
   if (run->precision != CFS_PREC_F32)
     return fail(CFS_E_UNSUPPORTED, "the Gaussian splat computes positions in FP32");
   if (img->kind != CFS_IMAGE_F32_DENSITY || img->channels != 1)
@@ -74,7 +78,7 @@ extern "C" size_t cfs_splat_workspace(const cfs_system *sys, const cfs_run *run,
   if (validate_gauss(sys, run, img, sigma_px)) return 0;
   if (run->n_iters == run->burn_in || run->n_points == 0) return 0;
   const GaussPlan p = gauss_plan(gauss_slice(run), run->n_iters, run->burn_in, img->width, img->height);
-  return align_up(p.records_bytes) + align_up(p.table_bytes);
+  return align_up(p.records_bytes) + 2 * align_up(p.table_bytes);
 }
 
 extern "C" int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
@@ -111,7 +115,9 @@ extern "C" int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_im
     j.ra.point_offset = run->point_offset + done;
     const GaussPlan p = gauss_plan(pts, run->n_iters, run->burn_in, img->width, img->height);
     j.gb.records = static_cast<float2 *>(workspace);
-    j.gb.tile_start = reinterpret_cast<uint32_t *>(static_cast<char *>(workspace) + align_up(p.records_bytes));
+    char *tables = static_cast<char *>(workspace) + align_up(p.records_bytes);
+    j.gb.chunk_start = reinterpret_cast<uint32_t *>(tables);
+    j.gb.tile_start = reinterpret_cast<uint32_t *>(tables + align_up(p.table_bytes));
     j.gb.n_chunks = no_splats ? 0 : p.n_chunks;
     j.gb.flushes = p.flushes;
     j.gb.n_tiles = p.n_tiles;

@@ -94,7 +94,7 @@ __device__ inline void flush_chunk(uint32_t *stage, uint32_t *cnt, uint32_t *wsu
 // Every thread of the workgroup calls it (it holds barriers).
 template <typename real, int DIM, int FINAL, int SEL>
 __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_maps, int n_search,
-                                   int top_step, const Window &win, const RunArgs &ra,
+                                   int top_step, int flags, const Window &win, const RunArgs &ra,
                                    const float *fparams, const BinArgs &ba, const Outputs &out,
                                    uint32_t block, uint32_t *stage, uint32_t *cnt, uint32_t *wsum) {
   const int tid = threadIdx.x;
@@ -121,13 +121,30 @@ __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_
       k = select_index<SEL>(u, th, n_maps, n_search, top_step);
       if (active && out.indices)
         out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
-      apply_map<real, DIM>(table, k, p);
+      apply_map<real, DIM>(table, k, p, flags);
+      if constexpr (DIM == 2 && FINAL != kFinalIdentity) {
+        if (flags & kFlagReuse) {
+          real g[2], dz;
+          final_transform<real, FINAL, DIM>(fparams, p, g, &dz);
+          p[0] = g[0];
+          p[1] = g[1];
+        }
+      }
       if (t > B) {
         uint32_t e = kInvalid;
         if (active) {
           real q[2];
           real depth = static_cast<real>(0);
-          final_transform<real, FINAL, DIM>(fparams, p, q, &depth);
+          if constexpr (DIM == 2 && FINAL != kFinalIdentity) {
+            if (flags & kFlagReuse) {
+              q[0] = p[0];
+              q[1] = p[1];
+            } else {
+              final_transform<real, FINAL, DIM>(fparams, p, q, &depth);
+            }
+          } else {
+            final_transform<real, FINAL, DIM>(fparams, p, q, &depth);
+          }
           int ix;
           const int pix = bin_pixel<real>(q, win, &ix);
           if (pix >= 0)
@@ -157,6 +174,156 @@ __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_
   if (out.dropped && dropped)
     __hip_atomic_fetch_add(out.dropped, static_cast<unsigned long long>(dropped),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Depth images (3D camera): the stage holds (pixel | index << 24, depth bits)
+// pairs; records keep the in-tile offset and the index in their first word.
+// ---------------------------------------------------------------------------
+__device__ inline void flush_depth_chunk(uint2 *stage, uint32_t *cnt, uint32_t *wsum, int used_slots,
+                                         uint32_t chunk, const BinArgs &ba) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const uint32_t total = block_exclusive_scan(cnt, ba.n_tiles, wsum);
+  const uint32_t base = chunk * kDCap;
+  uint32_t *row = ba.chunk_start + static_cast<size_t>(chunk) * (ba.n_tiles + 1);
+  for (uint32_t t = tid; t <= ba.n_tiles; t += kBinBlock) row[t] = base + (t < ba.n_tiles ? cnt[t] : total);
+  uint2 e[kDSlots];
+#pragma unroll
+  for (int i = 0; i < kDSlots; ++i)
+    e[i] = i < used_slots ? stage[i * kBinBlock + tid] : make_uint2(kInvalid, 0u);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kDSlots; ++i) {
+    if (e[i].x != kInvalid) {
+      const uint32_t pix = e[i].x & 0xFFFFFFu;
+      stage[atomicAdd(&cnt[pix >> kDTileBits], 1u)] = e[i];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = tid; i < total; i += kBinBlock) {
+    const uint2 v = stage[i];
+    const uint32_t off = v.x & (kDTileElems - 1);
+    const uint32_t k = v.x >> 24;
+    ba.drecords[static_cast<size_t>(base) + i] = make_uint2(off | (k << kDTileBits), v.y);
+  }
+  for (uint32_t t = tid; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
+  __syncthreads();
+}
+
+// One block of kBinBlock points of a 3D run with the twist/camera transform
+// and the binned depth splat (same arithmetic as the direct depth path).
+template <typename real, int SEL>
+__device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_maps, int n_search,
+                                  int top_step, const Window &win, const RunArgs &ra,
+                                  const float *fparams, float near_plane, const BinArgs &ba,
+                                  const Outputs &out, uint32_t block, uint2 *stage, uint32_t *cnt,
+                                  uint32_t *wsum) {
+  const int tid = threadIdx.x;
+  const uint32_t n = block * kBinBlock + tid;
+  const bool active = n < ra.n_points;
+  const uint32_t pid = ra.point_offset + (active ? n : 0u);
+  const uint32_t T = ra.n_iters, B = ra.burn_in;
+  real p[3];
+  initial_point<real, 3>(pid, ra.instance, ra.k0, ra.k1, p);
+  int k = 0;
+  uint32_t dropped = 0;
+  int slot = 0;
+  uint32_t chunk = block * ba.flushes;
+  for (uint32_t t0 = 0; t0 < T; t0 += 4) {
+    const Block4 blk = philox10(pid, t0 >> 2, ra.instance, 0u, ra.k0, ra.k1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t = t0 + j + 1;
+      if (t > T) break;
+      k = select_index<SEL>(word_of(blk, j), th, n_maps, n_search, top_step);
+      if (active && out.indices)
+        out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
+      apply_map<real, 3>(table, k, p);
+      if (t > B) {
+        uint2 e = make_uint2(kInvalid, 0u);
+        if (active) {
+          real q[2];
+          real depth = static_cast<real>(0);
+          final_transform<real, kFinalTwistCamera, 3>(fparams, p, q, &depth);
+          int ix;
+          int pix = bin_pixel<real>(q, win, &ix);
+          if (!(depth > static_cast<real>(near_plane))) pix = -1;
+          if (pix >= 0)
+            e = make_uint2(static_cast<uint32_t>(pix) | (static_cast<uint32_t>(k) << 24),
+                           __float_as_uint(static_cast<float>(depth)));
+          else
+            ++dropped;
+        }
+        stage[slot * kBinBlock + tid] = e;
+        if (e.x != kInvalid) atomicAdd(&cnt[(e.x & 0xFFFFFFu) >> kDTileBits], 1u);
+        if (++slot == kDSlots) {
+          flush_depth_chunk(stage, cnt, wsum, slot, chunk, ba);
+          slot = 0;
+          ++chunk;
+        }
+      }
+    }
+  }
+  if (slot > 0) flush_depth_chunk(stage, cnt, wsum, slot, chunk, ba);
+  if (!active) return;
+  if (out.final_points) {
+    real *fp = static_cast<real *>(out.final_points) + static_cast<size_t>(n) * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fp[c] = p[c];
+  }
+  if (out.last_index) out.last_index[n] = static_cast<uint8_t>(k);
+  if (out.dropped && dropped)
+    __hip_atomic_fetch_add(out.dropped, static_cast<unsigned long long>(dropped),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Depth tile t: LDS minimum of the keys (depth bits << 32 | index) and LDS
+// counts of every chunk's records, then merged into the image (min) and the
+// density (sum).  Every thread calls it; keys/counts are kDTileElems each.
+__device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
+                                             const uint32_t *__restrict__ tile_start,
+                                             uint32_t n_chunks, uint32_t elems,
+                                             unsigned long long *__restrict__ img,
+                                             uint32_t *__restrict__ density, uint32_t t,
+                                             unsigned long long *keys, uint32_t *counts) {
+  const int tid = threadIdx.x;
+  for (uint32_t i = tid; i < kDTileElems; i += kDAccBlock) {
+    keys[i] = ~0ull;
+    counts[i] = 0u;
+  }
+  __syncthreads();
+  const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
+  const uint32_t *row1 = row0 + n_chunks;
+  for (uint32_t c = tid; c < n_chunks; c += kDAccBlock) {
+    const uint32_t s = row0[c], e = row1[c];
+    for (uint32_t i = s; i < e; i += 4u) {
+      uint2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = i + u < e ? rec[i + u] : make_uint2(kInvalid, 0u);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (v[u].x == kInvalid) continue;
+        const uint32_t off = v[u].x & (kDTileElems - 1);
+        const unsigned long long key =
+            (static_cast<unsigned long long>(v[u].y) << 32) | (v[u].x >> kDTileBits);
+        atomicMin(&keys[off], key);
+        atomicAdd(&counts[off], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t base = t * kDTileElems;
+  const uint32_t len = min(kDTileElems, elems - base);
+  for (uint32_t i = tid; i < len; i += kDAccBlock) {
+    const uint32_t c = counts[i];
+    if (c) {
+      const unsigned long long k = keys[i];
+      if (k < img[base + i]) img[base + i] = k;
+      density[base + i] += c;
+    }
+  }
+  __syncthreads();
 }
 
 // Image tile t of one run: LDS histogram of the tile's records from every

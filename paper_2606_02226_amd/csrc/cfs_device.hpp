@@ -97,18 +97,46 @@ __device__ __forceinline__ int select_index(uint32_t u, const uint32_t *th, int 
 }
 
 // ---------------------------------------------------------------------------
-// Map table rows in LDS.  2D FP32 rows are 8 floats (two 16-byte reads);
-// 2D FP64 rows are 6 doubles; 3D rows hold A row-major then b.
+// Map table rows in LDS.  2D rows are 8 values: a00 a01 a10 a11 b0 b1, the
+// map kind (1 = circle) and padding; 3D rows hold A row-major then b.
 // ---------------------------------------------------------------------------
 template <typename real, int DIM>
 struct RowStride {
-  static constexpr int value = (DIM == 2) ? (sizeof(real) == 4 ? 8 : 6) : 12;
+  static constexpr int value = (DIM == 2) ? 8 : 12;
 };
 
+__device__ __forceinline__ float atan2_r(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double atan2_r(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ void sincos_m(float a, float *s, float *c) { sincosf(a, s, c); }
+__device__ __forceinline__ void sincos_m(double a, double *s, double *c) { sincos(a, s, c); }
+
+// The circle map of Section 3's circle equation (reading in cfs.h): radius
+// sqrt(v), angle pi (u + f) for u = |p|^2 and v = polar angle / (2 pi).
+template <typename real>
+__device__ __forceinline__ void circle_map(real f, real p[2]) {
+  const real two_pi = static_cast<real>(6.283185307179586476925286766559);
+  const real u = p[0] * p[0] + p[1] * p[1];
+  real th = atan2_r(p[1], p[0]);
+  if (th < static_cast<real>(0)) th += two_pi;
+  const real r2 = sqrt(th / two_pi);
+  const real th2 = static_cast<real>(0.5) * two_pi * (u + f);
+  real s, c;
+  sincos_m(th2, &s, &c);
+  p[0] = r2 * c;
+  p[1] = r2 * s;
+}
+
+// Apply map k.  `flags & kFlagCircle` (uniform) says whether any map is not
+// affine; the branch on the kind then diverges only where a wave holds both.
 template <typename real, int DIM>
-__device__ __forceinline__ void apply_map(const real *__restrict__ table, int k, real p[DIM]) {
+__device__ __forceinline__ void apply_map(const real *__restrict__ table, int k, real p[DIM],
+                                          int flags = 0) {
   const real *r = table + k * RowStride<real, DIM>::value;
   if constexpr (DIM == 2) {
+    if ((flags & kFlagCircle) && r[6] != static_cast<real>(0)) {
+      circle_map<real>(r[4], p);
+      return;
+    }
     const real x = p[0], y = p[1];
     p[0] = r[0] * x + r[1] * y + r[4];
     p[1] = r[2] * x + r[3] * y + r[5];
@@ -130,7 +158,10 @@ __device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
     const int m = i / S, c = i % S;
     real v = static_cast<real>(0);
     if constexpr (DIM == 2) {
-      if (c < 6) v = static_cast<real>(mt.coef[m * C + c]);
+      if (c < 6)
+        v = static_cast<real>(mt.coef[m * C + c]);
+      else if (c == 6)
+        v = static_cast<real>((mt.circle_mask >> m) & 1ull);
     } else {
       v = static_cast<real>(mt.coef[m * C + c]);
     }

@@ -10,7 +10,7 @@ namespace cfs {
 // atomic per splat).  table/th hold the map table in LDS.
 template <typename real, int DIM, int FINAL, int SEL, bool DEPTH>
 __device__ void chaos_direct_point(const real *table, const uint32_t *th, int n_maps, int n_search,
-                                   int top_step, const Window &win, const RunArgs &ra,
+                                   int top_step, int flags, const Window &win, const RunArgs &ra,
                                    const float *fparams, void *img, uint32_t *density,
                                    float near_plane, const Outputs &out, uint32_t n) {
   if (n >= ra.n_points) return;
@@ -32,11 +32,28 @@ __device__ void chaos_direct_point(const real *table, const uint32_t *th, int n_
       const uint32_t u = word_of(blk, j);
       k = select_index<SEL>(u, th, n_maps, n_search, top_step);
       if (out.indices) out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
-      apply_map<real, DIM>(table, k, p);
+      apply_map<real, DIM>(table, k, p, flags);
+      if constexpr (DIM == 2 && FINAL != kFinalIdentity) {
+        if (flags & kFlagReuse) {
+          real g[2], dz;
+          final_transform<real, FINAL, DIM>(fparams, p, g, &dz);
+          p[0] = g[0];
+          p[1] = g[1];
+        }
+      }
       if (t > B) {
         real q[2];
         real depth = static_cast<real>(0);
-        final_transform<real, FINAL, DIM>(fparams, p, q, &depth);
+        if constexpr (DIM == 2 && FINAL != kFinalIdentity) {
+          if (flags & kFlagReuse) {
+            q[0] = p[0];
+            q[1] = p[1];
+          } else {
+            final_transform<real, FINAL, DIM>(fparams, p, q, &depth);
+          }
+        } else {
+          final_transform<real, FINAL, DIM>(fparams, p, q, &depth);
+        }
         int ix;
         int pix = bin_pixel<real>(q, win, &ix);
         if constexpr (DEPTH) {

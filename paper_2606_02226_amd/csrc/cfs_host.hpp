@@ -36,7 +36,8 @@ struct BinPlan {
   uint32_t blocks, flushes, n_chunks, n_tiles, elems;
   size_t records_bytes, table_bytes;
 };
-BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems);
+BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems,
+                 bool depth = false);
 
 hipError_t launch_chaos_binned(const ChaosJob &job, hipStream_t stream);
 hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,

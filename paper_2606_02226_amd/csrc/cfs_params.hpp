@@ -17,6 +17,11 @@ constexpr int kFinalStretch = 3;
 // and the finite selection thresholds.  n_search == 0 selects with equal
 // probabilities; otherwise thresh[0 .. n_search-2] are the thresholds that
 // are below 2^32 and the draw picks among the first n_search maps.
+// MapTable::flags: some map is a circle map (see circle_mask); the composed
+// transform is fed back into the iteration instead of applied to a copy.
+constexpr int32_t kFlagCircle = 1;
+constexpr int32_t kFlagReuse = 2;
+
 template <int DIM>
 struct MapTable {
   float coef[kMaxMaps * DIM * (DIM + 1)];
@@ -24,6 +29,8 @@ struct MapTable {
   int32_t n_maps;
   int32_t n_search;
   int32_t top_step;  // largest power of two <= n_search - 1 (search start)
+  int32_t flags;     // kFlagCircle | kFlagReuse (uniform per system)
+  uint64_t circle_mask;  // bit m: map m is a circle map
 };
 
 struct Window {
@@ -55,8 +62,18 @@ constexpr uint32_t kTileElems = 1u << kTileBits;
 constexpr int kMaxTiles = 2048;  // images of up to 2^25 elements
 constexpr int kAccBlock = 512;
 
+// Binned depth splat: records are (pixel | index << 24, FP32 depth bits),
+// kDSlots per lane per chunk, sorted by tiles of kDTileElems pixels whose
+// u64 keys and u32 counts fit in LDS together.
+constexpr int kDSlots = 12;
+constexpr uint32_t kDCap = static_cast<uint32_t>(kBinBlock) * kDSlots;
+constexpr int kDTileBits = 13;
+constexpr uint32_t kDTileElems = 1u << kDTileBits;
+constexpr int kDAccBlock = 512;
+
 struct BinArgs {
   uint16_t *records;     // [n_chunks][kChunkCap] in-tile offsets, runs by tile
+  uint2 *drecords;       // depth images: [n_chunks][kDCap] (offset | index << 13, depth)
   uint32_t *chunk_start; // [n_chunks][n_tiles + 1]: run starts as the chunks write them
   uint32_t *tile_start;  // [n_tiles + 1][n_chunks]: the same, transposed for the accumulate
   uint32_t n_chunks;     // chunks of this launch (= blocks * flushes)
@@ -65,9 +82,9 @@ struct BinArgs {
   uint32_t elems;        // image elements (channels * height * width)
 };
 
-// Gaussian splat: 1024-lane workgroups collect kGSlots splats per lane as
+// Gaussian splat: 512-lane workgroups collect kGSlots splats per lane as
 // (x, y) pixel-coordinate records, sorted by 32x32-pixel tile.
-constexpr int kGBlock = 1024;
+constexpr int kGBlock = 512;
 constexpr int kGSlots = 12;
 constexpr uint32_t kGCap = static_cast<uint32_t>(kGBlock) * kGSlots;
 constexpr int kGTileLog = 5;
@@ -88,7 +105,8 @@ struct GaussParams {
 
 struct GaussBin {
   float2 *records;       // [n_chunks][kGCap] pixel coordinates, runs by tile
-  uint32_t *tile_start;  // [n_tiles + 1][n_chunks]
+  uint32_t *chunk_start; // [n_chunks][n_tiles + 1] as the chunks write them
+  uint32_t *tile_start;  // [n_tiles + 1][n_chunks] transposed for the accumulate
   uint32_t n_chunks, flushes, n_tiles;
 };
 

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_emit(const InstDesc *__rest
     Outputs out{nullptr, nullptr, nullptr, d.dropped};
     for (uint32_t b = 0; b < item.n_blocks; ++b)
       chaos_binned_block<real, 2, kFinalIdentity, kSelRuntime>(
-          table, th, d.mt.n_maps, d.mt.n_search, d.mt.top_step, d.win, d.ra, nullptr, ba, out,
+          table, th, d.mt.n_maps, d.mt.n_search, d.mt.top_step, d.mt.flags, d.win, d.ra, nullptr,
+          ba, out,
           item.first_block + b, stage, cnt, wsum);
     __syncthreads();
   }
@@ -109,7 +110,8 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_direct(const InstDesc *__re
     Outputs out{nullptr, nullptr, nullptr, d.dropped};
     for (uint32_t b = 0; b < item.n_blocks; ++b)
       chaos_direct_point<real, 2, kFinalIdentity, kSelRuntime, false>(
-          table, th, d.mt.n_maps, d.mt.n_search, d.mt.top_step, d.win, d.ra, nullptr, d.img,
+          table, th, d.mt.n_maps, d.mt.n_search, d.mt.top_step, d.mt.flags, d.win, d.ra, nullptr,
+          d.img,
           nullptr, 0.0f, out, (item.first_block + b) * kBinBlock + threadIdx.x);
     __syncthreads();
   }

@@ -30,8 +30,37 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_binned(MapTable<DIM> mt, Wi
   load_table<real, DIM>(mt, table, th);
   for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
   __syncthreads();
-  chaos_binned_block<real, DIM, FINAL, EQUAL>(table, th, mt.n_maps, mt.n_search, mt.top_step, win,
-                                              ra, fa.p, ba, out, blockIdx.x, stage, cnt, wsum);
+  chaos_binned_block<real, DIM, FINAL, EQUAL>(table, th, mt.n_maps, mt.n_search, mt.top_step,
+                                              mt.flags, win, ra, fa.p, ba, out, blockIdx.x, stage,
+                                              cnt, wsum);
+}
+
+template <typename real, bool EQUAL>
+__global__ __launch_bounds__(kBinBlock) void k_chaos_depth_binned(MapTable<3> mt, Window win,
+                                                                  RunArgs ra, FinalArgs fa,
+                                                                  float near_plane, BinArgs ba,
+                                                                  Outputs out) {
+  __shared__ real table[kMaxMaps * RowStride<real, 3>::value];
+  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint2 stage[kDCap];
+  __shared__ uint32_t cnt[kMaxTiles];
+  __shared__ uint32_t wsum[kWaves + 1];
+  load_table<real, 3>(mt, table, th);
+  for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
+  __syncthreads();
+  chaos_depth_block<real, EQUAL ? kSelEqual : kSelTable>(table, th, mt.n_maps, mt.n_search,
+                                                         mt.top_step, win, ra, fa.p, near_plane,
+                                                         ba, out, blockIdx.x, stage, cnt, wsum);
+}
+
+__global__ __launch_bounds__(kDAccBlock) void k_depth_accumulate(const uint2 *__restrict__ rec,
+                                                                 const uint32_t *__restrict__ tile_start,
+                                                                 uint32_t n_chunks, uint32_t elems,
+                                                                 unsigned long long *img,
+                                                                 uint32_t *density) {
+  __shared__ unsigned long long keys[kDTileElems];
+  __shared__ uint32_t counts[kDTileElems];
+  depth_tile_accumulate(rec, tile_start, n_chunks, elems, img, density, blockIdx.x, keys, counts);
 }
 
 // One workgroup per image tile.
@@ -58,14 +87,16 @@ hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, ui
   return hipGetLastError();
 }
 
-BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems) {
+BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems, bool depth) {
   BinPlan bp{};
+  const uint32_t slots = depth ? kDSlots : kBinSlots;
   bp.blocks = (points + kBinBlock - 1) / kBinBlock;
-  bp.flushes = (n_iters - burn_in + kBinSlots - 1) / kBinSlots;
+  bp.flushes = (n_iters - burn_in + slots - 1) / slots;
   bp.n_chunks = bp.blocks * bp.flushes;
-  bp.n_tiles = (elems + kTileElems - 1) / kTileElems;
+  bp.n_tiles = depth ? (elems + kDTileElems - 1) / kDTileElems : (elems + kTileElems - 1) / kTileElems;
   bp.elems = elems;
-  bp.records_bytes = static_cast<size_t>(bp.n_chunks) * kChunkCap * sizeof(uint16_t);
+  bp.records_bytes = depth ? static_cast<size_t>(bp.n_chunks) * kDCap * sizeof(uint2)
+                           : static_cast<size_t>(bp.n_chunks) * kChunkCap * sizeof(uint16_t);
   bp.table_bytes = static_cast<size_t>(bp.n_tiles + 1) * bp.n_chunks * sizeof(uint32_t);  // each of two
   return bp;
 }
@@ -103,8 +134,30 @@ static hipError_t launch_binned_real(const ChaosJob &j, hipStream_t s) {
   }
 }
 
+template <typename real>
+static hipError_t launch_depth_binned(const ChaosJob &j, hipStream_t s) {
+  const uint32_t blocks = (j.ra.n_points + kBinBlock - 1) / kBinBlock;
+  if (j.equal)
+    hipLaunchKernelGGL((k_chaos_depth_binned<real, true>), dim3(blocks), dim3(kBinBlock), 0, s, j.mt3,
+                       j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
+  else
+    hipLaunchKernelGGL((k_chaos_depth_binned<real, false>), dim3(blocks), dim3(kBinBlock), 0, s,
+                       j.mt3, j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || j.ba.n_chunks == 0) return e;
+  e = launch_transpose(j.ba.chunk_start, j.ba.tile_start, j.ba.n_chunks, j.ba.n_tiles + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_depth_accumulate, dim3(j.ba.n_tiles), dim3(kDAccBlock), 0, s, j.ba.drecords,
+                     j.ba.tile_start, j.ba.n_chunks, j.ba.elems,
+                     static_cast<unsigned long long *>(j.img), j.density);
+  return hipGetLastError();
+}
+
 hipError_t launch_chaos_binned(const ChaosJob &job, hipStream_t stream) {
   if (job.ra.n_points == 0) return hipSuccess;
+  if (job.depth)
+    return job.precision == 1 ? launch_depth_binned<double>(job, stream)
+                              : launch_depth_binned<float>(job, stream);
   return job.precision == 1 ? launch_binned_real<double>(job, stream)
                             : launch_binned_real<float>(job, stream);
 }

@@ -23,7 +23,8 @@ __global__ __launch_bounds__(kChaosBlock) void k_chaos(MapTable<DIM> mt, Window 
   load_table<real, DIM>(mt, table, th);
   __syncthreads();
   chaos_direct_point<real, DIM, FINAL, EQUAL, DEPTH>(table, th, mt.n_maps, mt.n_search, mt.top_step,
-                                                     win, ra, fa.p, img, density, near_plane, out,
+                                                     mt.flags, win, ra, fa.p, img, density,
+                                                     near_plane, out,
                                                      blockIdx.x * kChaosBlock + threadIdx.x);
 }
 

@@ -41,12 +41,18 @@ __device__ __forceinline__ uint32_t gauss_tile_of(float2 r, const GaussParams &g
   return static_cast<uint32_t>((j0 >> kGTileLog) * gp.tiles_x + (i0 >> kGTileLog));
 }
 
+constexpr int kGScanPer = (kGMaxTiles + kGBlock - 1) / kGBlock;
+
 __device__ uint32_t gblock_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsum) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const uint32_t i0 = 2u * tid, i1 = i0 + 1u;
-  const uint32_t v0 = i0 < n ? a[i0] : 0u;
-  const uint32_t v1 = i1 < n ? a[i1] : 0u;
-  const uint32_t s = v0 + v1;
+  const uint32_t i0 = static_cast<uint32_t>(tid) * kGScanPer;
+  uint32_t v[kGScanPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kGScanPer; ++q) {
+    v[q] = i0 + q < n ? a[i0 + q] : 0u;
+    s += v[q];
+  }
   uint32_t incl = s;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -67,9 +73,12 @@ __device__ uint32_t gblock_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsu
     if (lane == kGWaves - 1) wsum[kGWaves] = xi;
   }
   __syncthreads();
-  const uint32_t excl = wsum[w] + incl - s;
-  if (i0 < n) a[i0] = excl;
-  if (i1 < n) a[i1] = excl + v0;
+  uint32_t run = wsum[w] + incl - s;
+#pragma unroll
+  for (int q = 0; q < kGScanPer; ++q) {
+    if (i0 + q < n) a[i0 + q] = run;
+    run += v[q];
+  }
   const uint32_t total = wsum[kGWaves];
   __syncthreads();
   return total;
@@ -90,9 +99,8 @@ __device__ void gauss_flush(float2 *stage, uint32_t *cnt, uint32_t *wsum, int us
   __syncthreads();  // every count complete before the scan reads them
   const uint32_t total = gblock_exclusive_scan(cnt, gb.n_tiles, wsum);
   const uint32_t base = chunk * kGCap;
-  for (uint32_t t = tid; t <= gb.n_tiles; t += kGBlock)
-    gb.tile_start[static_cast<size_t>(t) * gb.n_chunks + chunk] =
-        base + (t < gb.n_tiles ? cnt[t] : total);
+  uint32_t *row = gb.chunk_start + static_cast<size_t>(chunk) * (gb.n_tiles + 1);
+  for (uint32_t t = tid; t <= gb.n_tiles; t += kGBlock) row[t] = base + (t < gb.n_tiles ? cnt[t] : total);
 #pragma unroll
   for (int i = 0; i < kGSlots; ++i)
     if (tl[i] != kGInvalid) stage[cnt[tl[i]] + r[i]] = e[i];
@@ -193,43 +201,35 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
                                                                  uint32_t n_chunks, GaussParams gp,
                                                                  float *__restrict__ dens) {
   __shared__ float acc[kGTile * kGTile];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x;
   const int tx = blockIdx.x % gp.tiles_x, ty = blockIdx.x / gp.tiles_x;
   const int x0 = tx * kGTile, y0 = ty * kGTile;
   const int xlo = x0, xhi = min(x0 + kGTile, gp.width);
   const int ylo = y0, yhi = min(y0 + kGTile, gp.height);
   for (int i = tid; i < kGTile * kGTile; i += kGAccBlock) acc[i] = 0.0f;
   __syncthreads();
-  constexpr int kWav = kGAccBlock / 64;
-  for (int src = 0; src < 4; ++src) {
-    const int sx = tx - (src & 1), sy = ty - (src >> 1);
-    if (sx < 0 || sy < 0) continue;
-    const uint32_t st = static_cast<uint32_t>(sy * gp.tiles_x + sx);
-    const uint32_t *row0 = tile_start + static_cast<size_t>(st) * n_chunks;
-    const uint32_t *row1 = row0 + n_chunks;
-    for (uint32_t cb = static_cast<uint32_t>(w) * 64u; cb < n_chunks; cb += kWav * 64u) {
-      const uint32_t c = cb + lane;
-      const uint32_t s = c < n_chunks ? row0[c] : 0u;
-      const uint32_t e = c < n_chunks ? row1[c] : 0u;
-      for (int j = 0; j < 64; ++j) {
-        const uint32_t sj = __builtin_amdgcn_readlane(s, j);
-        const uint32_t ej = __builtin_amdgcn_readlane(e, j);
-        for (uint32_t i = sj + lane; i < ej; i += 64) {
-          const float2 r = rec[i];
-          const int i0 = first_tap(r.x, gp.R), j0 = first_tap(r.y, gp.R);
-          if (i0 >= xhi || i0 + TAPS <= xlo || j0 >= yhi || j0 + TAPS <= ylo) continue;
-          float gx[TAPS], gy[TAPS];
-          tap_weights<TAPS>(r.x, i0, xlo, xhi, gp, gx);
-          tap_weights<TAPS>(r.y, j0, ylo, yhi, gp, gy);
+  // each lane walks the runs of its chunks in the tile and its left, upper
+  // and upper-left neighbours
+  for (uint32_t c = tid; c < n_chunks; c += kGAccBlock) {
+    for (int src = 0; src < 4; ++src) {
+      const int sx = tx - (src & 1), sy = ty - (src >> 1);
+      if (sx < 0 || sy < 0) continue;
+      const uint32_t *row0 = tile_start + static_cast<size_t>(sy * gp.tiles_x + sx) * n_chunks;
+      const uint32_t s = row0[c], e = row0[n_chunks + c];
+      for (uint32_t i = s; i < e; ++i) {
+        const float2 r = rec[i];
+        const int i0 = first_tap(r.x, gp.R), j0 = first_tap(r.y, gp.R);
+        if (i0 >= xhi || i0 + TAPS <= xlo || j0 >= yhi || j0 + TAPS <= ylo) continue;
+        float gx[TAPS], gy[TAPS];
+        tap_weights<TAPS>(r.x, i0, xlo, xhi, gp, gx);
+        tap_weights<TAPS>(r.y, j0, ylo, yhi, gp, gy);
 #pragma unroll
-          for (int b = 0; b < TAPS; ++b) {
-            if (gy[b] == 0.0f) continue;
-            const float wy = gy[b] * gp.weight;
+        for (int b = 0; b < TAPS; ++b) {
+          if (gy[b] == 0.0f) continue;
+          const float wy = gy[b] * gp.weight;
 #pragma unroll
-            for (int a = 0; a < TAPS; ++a)
-              if (gx[a] != 0.0f)
-                atomicAdd(&acc[(j0 + b - y0) * kGTile + (i0 + a - x0)], gx[a] * wy);
-          }
+          for (int a = 0; a < TAPS; ++a)
+            if (gx[a] != 0.0f) atomicAdd(&acc[(j0 + b - y0) * kGTile + (i0 + a - x0)], gx[a] * wy);
         }
       }
     }
@@ -432,6 +432,8 @@ hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
     hipLaunchKernelGGL(k_splat_emit<false>, dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp, j.gb,
                        j.ck, j.dropped);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_transpose(j.gb.chunk_start, j.gb.tile_start, j.gb.n_chunks, j.gb.n_tiles + 1, s);
   if (e != hipSuccess) return e;
   if (j.gp.taps <= 6)
     hipLaunchKernelGGL(k_splat_accumulate<6>, dim3(j.gb.n_tiles), dim3(kGAccBlock), 0, s,

@@ -1,7 +1,8 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
 include/cfs.h declares, and rejects invalid arguments on the host before
-anything is enqueued.  Every invalid call below fails validation by
-construction (device pointers are NULL), so no kernel can be launched."""
+anything is enqueued.  Every call below fails host validation by construction
+(device pointers are NULL, or a placeholder address together with another
+argument that is invalid), so no kernel is ever launched.""" 
 import ctypes as C
 import os
 import re
@@ -135,3 +136,106 @@ def test_null_structs(L):
 def test_philox_dump_rejects_null(L):
     lib = L.load()
     assert lib.cfs_philox_dump(0, None, None, 4, None) == L.CFS_E_INVALID
+
+
+PLACEHOLDER = 0x1000  # never dereferenced: each call using it fails validation
+
+
+def _dens_image(L, W=16, H=16):
+    return L.CfsImage(1, W, H, 1, (C.c_float * 2)(0, 0), (C.c_float * 2)(1, 1), 0.0,
+                      PLACEHOLDER, None, None)
+
+
+def test_splat_validation(L):
+    lib = L.load()
+    s, keep = _system(L, n=4)
+    r = _run(L, n_points=16, n_iters=8, burn_in=2)
+    img = _dens_image(L)
+    # sigma outside (0, 2.5]
+    assert lib.cfs_splat(C.byref(s), C.byref(r), C.byref(img), 0.0, None, 8, None, 0,
+                         None) == L.CFS_E_INVALID
+    assert "sigma" in lib.cfs_last_error().decode()
+    assert lib.cfs_splat(C.byref(s), C.byref(r), C.byref(img), 3.0, None, 8, None, 0,
+                         None) == L.CFS_E_INVALID
+    # FP64 positions are not offered by the differentiable form
+    r64 = _run(L, n_points=16, n_iters=8, burn_in=2, precision=1)
+    assert lib.cfs_splat(C.byref(s), C.byref(r64), C.byref(img), 1.0, None, 8, None, 0,
+                         None) == L.CFS_E_UNSUPPORTED
+    # a count image is not a density
+    cimg = _image(L)
+    cimg.data = PLACEHOLDER
+    assert lib.cfs_splat(C.byref(s), C.byref(r), C.byref(cimg), 1.0, None, 8, None, 0,
+                         None) == L.CFS_E_INVALID
+
+
+def test_splat_backward_validation(L):
+    lib = L.load()
+    s9, keep = _system(L, n=9)
+    r = _run(L, n_points=16, n_iters=8, burn_in=2)
+    img = _dens_image(L)
+    img.data = None
+    # image data NULL fails validation first
+    assert lib.cfs_splat_backward(C.byref(s9), C.byref(r), C.byref(img), 1.0, None, None, 8,
+                                  None, None, 0, None) == L.CFS_E_INVALID
+    # missing upstream gradient / checkpoints (data pointer only checked for NULL)
+    img.data = PLACEHOLDER
+    s4, keep4 = _system(L, n=4)
+    assert lib.cfs_splat_backward(C.byref(s4), C.byref(r), C.byref(img), 1.0, None, None, 8,
+                                  None, None, 0, None) == L.CFS_E_INVALID
+    assert "required" in lib.cfs_last_error().decode()
+    # more than 8 maps
+    assert lib.cfs_splat_backward(C.byref(s9), C.byref(r), C.byref(img), 1.0, None, None, 8,
+                                  None, None, 0, None) == L.CFS_E_UNSUPPORTED
+
+
+def test_batch_validation(L):
+    lib = L.load()
+    out = C.c_void_p()
+    assert lib.cfs_batch_create(None, 0, None, C.byref(out)) == L.CFS_E_INVALID
+    items = (L.CfsBatchItem * 1)()
+    s, keep = _system(L, n=3)
+    items[0].sys = s
+    items[0].run = _run(L)
+    items[0].img = _image(L)  # data NULL
+    assert lib.cfs_batch_create(items, 1, None, C.byref(out)) == L.CFS_E_INVALID
+    assert "batch item 0" in lib.cfs_last_error().decode()
+    s3, keep3 = _system(L, dim=3, n=3)
+    items[0].sys = s3
+    assert lib.cfs_batch_create(items, 1, None, C.byref(out)) != L.CFS_OK
+    assert lib.cfs_batch_run(None, None) == L.CFS_E_INVALID
+    assert lib.cfs_batch_plan(None, None) == L.CFS_E_INVALID
+    assert lib.cfs_batch_update(None, 0, None, None) == L.CFS_E_INVALID
+    lib.cfs_batch_destroy(None)
+
+
+def test_workspace_queries_on_invalid_input(L):
+    lib = L.load()
+    assert lib.cfs_chaos_game_workspace(None, None, None) == 0
+    assert lib.cfs_splat_workspace(None, None, None, 1.0) == 0
+    assert lib.cfs_splat_backward_workspace(None, None) == 0
+
+
+def test_bad_map_kind(L):
+    lib = L.load()
+    s, keep = _system(L, n=3)
+    kinds = (C.c_int32 * 3)(0, 7, 0)
+    s.kind = kinds
+    assert _call(L, s, _run(L), _image(L)) == L.CFS_E_INVALID
+    assert "not a map kind" in lib.cfs_last_error().decode()
+    s3, keep3 = _system(L, dim=3, n=3)
+    k3 = (C.c_int32 * 3)(1, 0, 0)
+    s3.kind = k3
+    assert _call(L, s3, _run(L), _image(L)) == L.CFS_E_INVALID
+    assert "dim 2" in lib.cfs_last_error().decode()
+
+
+def test_bad_compose(L):
+    lib = L.load()
+    s, keep = _system(L, n=3)
+    s.compose = 2
+    assert _call(L, s, _run(L), _image(L)) == L.CFS_E_INVALID
+    assert "composition mode" in lib.cfs_last_error().decode()
+    s3, keep3 = _system(L, dim=3, n=3)
+    s3.compose = 1
+    assert _call(L, s3, _run(L), _image(L)) == L.CFS_E_INVALID
+    assert "dim 2" in lib.cfs_last_error().decode()

@@ -354,3 +354,127 @@ def test_full_size_cfs_square_sampled(api, orc):
         assert np.max(np.abs(r["final"][0] - fs[i])) <= 1e-12
     direct = _image_of(api, w, "f64", "direct")
     assert np.array_equal(direct["image"], got["image"])
+
+
+# ---------------------------------------------------------------------------
+# Binned depth splat (3D camera): bit-identical to the direct depth splat
+# ---------------------------------------------------------------------------
+def _depth_image(api, w, precision, splat_path, run=None):
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(w["system"], run or w["run"], img, precision=precision, splat_path=splat_path)
+    return img.to_numpy()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_depth_binned_equals_direct(api, precision):
+    w = W.menger(n_points=(1 << 18) + 3, side=1024)
+    a = _depth_image(api, w, precision, "direct")
+    b = _depth_image(api, w, precision, "binned")
+    assert np.array_equal(a["depth"], b["depth"])
+    assert np.array_equal(a["density"], b["density"])
+    assert a["dropped"] == b["dropped"]
+
+
+def test_depth_binned_vs_oracle(api, orc):
+    w = W.menger(n_points=1 << 14, side=1024)
+    got = _depth_image(api, w, "f64", "binned")
+    ref = orc.chaos_depth(w["system"], w["run"], w["image"], w["image"]["near"])
+    assert got["dropped"] == ref["dropped"]
+    assert np.array_equal(got["density"], ref["density"])
+    assert np.mean(got["depth"] == ref["depth"]) >= 1 - 1e-4
+
+
+def test_full_size_menger(api, orc):
+    """The 3D configuration at full size (2^26 points x 24 iterations, 4096^2):
+    binned == direct bit for bit, exact splat accounting, and sampled points'
+    final positions and last indices equal to the oracle's one by one."""
+    w = W.menger()
+    N, T, B = 1 << 26, 24, 8
+    img = api.Image(w["image"], device=_dev()).clear()
+    fin = torch.empty((N, 3), dtype=torch.float64, device=_dev())
+    last = torch.empty((N,), dtype=torch.uint8, device=_dev())
+    api.chaos_game(w["system"], w["run"], img, precision="f64", final=fin, last=last,
+                   splat_path="binned")
+    got = img.to_numpy()
+    assert int(got["density"].astype(np.int64).sum()) + got["dropped"] == N * (T - B)
+    direct = _depth_image(api, w, "f64", "direct")
+    assert np.array_equal(direct["depth"], got["depth"])
+    assert np.array_equal(direct["density"], got["density"])
+    rng = np.random.default_rng(3)
+    sample = np.sort(rng.choice(N, size=256, replace=False))
+    idx = torch.from_numpy(sample).to(_dev())
+    fs, ls = fin[idx].cpu().numpy(), last[idx].cpu().numpy()
+    for i, pid in enumerate(sample):
+        r = orc.chaos_depth(w["system"], dict(w["run"], n_points=1, point_offset=int(pid)),
+                            dict(w["image"], width=8, height=8), w["image"]["near"],
+                            want_final=True, want_last=True)
+        assert r["last"][0] == ls[i]
+        assert np.max(np.abs(r["final"][0] - fs[i])) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The paper's circle primitive (non-affine maps, mixed kinds)
+# ---------------------------------------------------------------------------
+def test_circle_fp64_parity(api, orc):
+    w = W.circle(n_points=1 << 14)
+    got = run_gpu(api, w, "f64", want_indices=True)
+    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True,
+                          want_last=True, want_indices=True)
+    assert np.array_equal(got["indices"], ref["indices"])
+    err = np.abs(got["final"] - ref["final"]).max(axis=1)
+    print(f"circle f64: max |dp| {err.max():.2e}, relL1 {rel_l1(got['image'], ref['image']):.2e}")
+    assert np.mean(err > 1e-9) <= 1e-3
+    assert rel_l1(got["image"], ref["image"]) <= 1e-4
+    assert got["dropped"] == ref["dropped"]
+
+
+def test_circle_fp32_indices_and_measure(api, orc):
+    w = W.circle(n_points=1 << 14)
+    got = run_gpu(api, w, "f32", want_indices=True)
+    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_indices=True)
+    assert np.array_equal(got["indices"], ref["indices"])
+    l1 = rel_l1(got["image"], ref["image"])
+    print(f"circle f32: relL1 {l1:.2e}")
+    P = got["final"]
+    u = P[:, 0] ** 2 + P[:, 1] ** 2
+    assert np.all(u <= 1.0 + 1e-6) and abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / u.size)
+
+
+@pytest.mark.parametrize("path", ["direct", "binned"])
+def test_mixed_kinds_parity(api, orc, path):
+    # two circle maps and two affine maps in one system: waves hold both kinds
+    w = W.circle(n_points=20000, extra_affine=2)
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(w["system"], w["run"], img, precision="f64", splat_path=path)
+    got = img.to_numpy()
+    ref = orc.chaos_count(w["system"], w["run"], w["image"])
+    assert rel_l1(got["image"], ref["image"]) <= 1e-4
+
+
+@pytest.mark.parametrize("path", ["direct", "binned"])
+@pytest.mark.parametrize("compose", ["copy", "reuse"])
+def test_composed_circle_parity(api, orc, compose, path):
+    # Section 3's composition figure: the swirl on a copy of the point or fed back
+    w = W.composed_circle(compose, n_points=20000)
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(w["system"], w["run"], img, precision="f64", splat_path=path)
+    got = img.to_numpy()
+    ref = orc.chaos_count(w["system"], w["run"], w["image"])
+    l1 = rel_l1(got["image"], ref["image"])
+    print(f"composed circle {compose} {path}: relL1 {l1:.2e}")
+    assert l1 <= 1e-4
+    assert got["dropped"] == ref["dropped"]
+
+
+def test_reuse_square_final_points(api, orc):
+    # the CFS square's swirl fed back into the iteration, FP64, per point
+    w = W.cfs_square(n_points=4096, side=256)
+    w["system"]["compose"] = "reuse"
+    got = run_gpu(api, w, "f64", want_indices=True)
+    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True,
+                          want_indices=True)
+    assert np.array_equal(got["indices"], ref["indices"])
+    err = np.abs(got["final"] - ref["final"]).max(axis=1)
+    print(f"reuse square f64: max |dp| {err.max():.2e}")
+    assert np.mean(err > 1e-9) <= 1e-3
+    assert rel_l1(got["image"], ref["image"]) <= 1e-4
