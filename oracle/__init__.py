@@ -34,7 +34,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cfs_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_cfs_oracle.so")
 
-FINAL_KINDS = {"identity": 0, "swirl": 1, "twist_camera": 2, "stretch": 3}
+FINAL_KINDS = {"identity": 0, "swirl": 1, "twist_camera": 2, "stretch": 3, "ring": 4}
 MAP_KINDS = {"affine": 0, "circle": 1}
 COMPOSE = {"copy": 0, "reuse": 1}
 
@@ -87,6 +87,7 @@ def _load():
         lib.orc_select_histogram.argtypes = [P, C.c_int, P]
         lib.orc_chaos_count.argtypes = [P, P, P, P, P, P, P, P, P]
         lib.orc_chaos_depth.argtypes = [P, P, P, C.c_float, P, P, P, P, P, P]
+        lib.orc_chaos_scene.argtypes = [P, P, C.c_int, P, P, P, P, P]
         lib.orc_splat_gauss.argtypes = [P, P, P, C.c_double, P, P]
         lib.orc_splat_gauss_backward.argtypes = [P, P, P, C.c_double, P, P]
         _lib = lib
@@ -216,6 +217,59 @@ def chaos_count(system, run, image, *, want_final=False, want_last=False,
     _check(rc, "chaos_count")
     return {"image": img, "final": fin, "last": last, "indices": idx,
             "splats": spl, "dropped": int(dropped[0])}
+
+
+class _Object(C.Structure):
+    _fields_ = [("final_kind", C.c_int32), ("final_params", C.POINTER(C.c_float)),
+                ("place", C.c_float * 6), ("channel", C.c_int32), ("n_copies", C.c_uint32),
+                ("copy_lo", C.c_float * 2), ("copy_span", C.c_float * 2),
+                ("scale_lo", C.c_float), ("scale_span", C.c_float)]
+
+
+def _objects(objects):
+    """ctypes array of the scene's objects (dicts with final_kind,
+    final_params, place, channel, n_copies, copy_lo, copy_hi, scale)."""
+    arr = (_Object * len(objects))()
+    keep = []
+    for o, ob in zip(arr, objects):
+        fp = np.zeros(24, np.float32)
+        src = np.asarray(ob.get("final_params", ()), np.float32).reshape(-1)
+        fp[: src.size] = src
+        keep.append(fp)
+        o.final_kind = FINAL_KINDS[ob.get("final_kind", "identity")]
+        o.final_params = fp.ctypes.data_as(C.POINTER(C.c_float))
+        pl = np.asarray(ob.get("place", (1, 0, 0, 1, 0, 0)), np.float32)
+        o.place = (C.c_float * 6)(*[float(v) for v in pl])
+        o.channel = int(ob.get("channel", 0))
+        o.n_copies = int(ob.get("n_copies", 1))
+        lo = np.asarray(ob.get("copy_lo", (0, 0)), np.float32)
+        hi = np.asarray(ob.get("copy_hi", (0, 0)), np.float32)
+        o.copy_lo = (C.c_float * 2)(*[float(v) for v in lo])
+        o.copy_span = (C.c_float * 2)(*[float(np.float32(h - l)) for l, h in zip(lo, hi)])
+        sc = np.asarray(ob.get("scale", (1, 1)), np.float32)
+        o.scale_lo = float(sc[0])
+        o.scale_span = float(np.float32(sc[1] - sc[0]))
+    return arr, keep
+
+
+def chaos_scene(system, objects, run, image, *, want_splats=False, out=None):
+    """Several objects from one 2D primitive (u32 count image, one channel per
+    object's ``channel``).  'splats' is [N][T-B][n_objects][2] in window
+    coordinates."""
+    lib = _load()
+    keep = _Keep(system)
+    objs, okeep = _objects(objects)
+    r = _run(run)
+    w = _window(image)
+    N, T, B = r.n_points, r.n_iters, r.burn_in
+    img = out if out is not None else np.zeros((w.channels, w.height, w.width), np.uint32)
+    assert img.dtype == np.uint32 and img.flags.c_contiguous
+    spl = np.zeros((N, T - B, len(objects), 2), np.float64) if want_splats else None
+    dropped = np.zeros(1, np.uint64)
+    rc = lib.orc_chaos_scene(C.byref(keep.s), objs, len(objects), C.byref(r), C.byref(w),
+                             _ptr(img), _ptr(spl), _ptr(dropped))
+    _check(rc, "chaos_scene")
+    return {"image": img, "splats": spl, "dropped": int(dropped[0])}
 
 
 def chaos_depth(system, run, image, near, *, want_final=False, want_last=False,

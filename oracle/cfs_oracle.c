@@ -44,6 +44,7 @@
 #define ORC_FINAL_SWIRL 1
 #define ORC_FINAL_TWIST_CAMERA 2
 #define ORC_FINAL_STRETCH 3
+#define ORC_FINAL_RING 4
 
 #define ORC_MAX_MAPS 64
 
@@ -231,6 +232,13 @@ static void apply_map(const orc_system *s, int k, double p[3]) {
  *               then a translation).
  *  STRETCH (2D) params {sx, sy}: q = (sx x, y - sy cos x)  (the stretch
  *               equation of Section 3 is sx = 2, sy = 1).
+ *  RING (2D)    params {r_in, r_out}: the point at radius r about the origin
+ *               moves along its ray to radius
+ *               R = sqrt(r_in^2 + (r_out^2 - r_in^2) r^2)  (the origin goes
+ *               to (r_in, 0)).  It sends the uniform unit disk to the uniform
+ *               annulus r_in <= R < r_out: the "rings" object of Section 3's
+ *               multiple-objects scene (a topologically non-trivial object
+ *               from the disk primitive; the paper gives no formula).
  *  TWIST_CAMERA (3D) params {kappa, cx, cy, cz, M[12], fx, fy}: twist the
  *               copy about the vertical axis through c by the angle
  *               kappa (y - cy), then map it to view space v = R w + tr with
@@ -254,6 +262,20 @@ static void final_transform(const orc_system *s, const double p[3], double q[2],
     case ORC_FINAL_STRETCH: {
       q[0] = (double)fp[0] * p[0];
       q[1] = p[1] - (double)fp[1] * cos(p[0]);
+      break;
+    }
+    case ORC_FINAL_RING: {
+      double ri = fp[0], ro = fp[1];
+      double r2 = p[0] * p[0] + p[1] * p[1];
+      double R = sqrt(ri * ri + (ro * ro - ri * ri) * r2);
+      if (r2 > 0.0) {
+        double r = sqrt(r2);
+        q[0] = R * (p[0] / r);
+        q[1] = R * (p[1] / r);
+      } else {
+        q[0] = R;
+        q[1] = 0.0;
+      }
       break;
     }
     case ORC_FINAL_TWIST_CAMERA: {
@@ -389,6 +411,114 @@ int orc_chaos_count(const orc_system *s, const orc_run *r, const orc_window *w,
     if (final_p)
       for (int c = 0; c < d; ++c) final_p[(size_t)n * d + c] = p[c];
     if (last_k) last_k[n] = (uint8_t)k;
+  }
+  if (dropped) *dropped += n_drop;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Several objects from one primitive (Section 3, "multiple objects from a   */
+/* single primitive", fig. "space"): after each step of the chaos game the   */
+/* point is repositioned once per object -- a transform of its own, then a   */
+/* placement -- and each object's copy is splatted, while the point itself   */
+/* keeps iterating.  Duplication (the "stars" of that scene): an object with */
+/* n_copies > 1 sends each splat to one copy, drawn from a random stream,    */
+/* and places copy c with offsets and a scale that another random stream     */
+/* derives from c alone, so every point agrees on where copy c is and no     */
+/* copy table is stored.  Readings (the paper gives no formulas):            */
+/*   object transform: one of the 2D final kinds, then q' = P q + t;         */
+/*   copy draw of iteration t: word (t-1) mod 4 of the Philox block          */
+/*     (pid, (t-1)/4, instance, 2); object o of the scene takes              */
+/*     c = floor(((2o + 1) u mod 2^32) n_copies / 2^32) (an odd multiplier   */
+/*     is a bijection of the words, so c is uniform for every object);       */
+/*   copy placement: Philox block (c, o, instance, 3); words 0, 1 and 2 give */
+/*     e_i = (w_i >> 8) 2^-24, offset = lo + span e_{0,1}, scale =           */
+/*     s_lo + s_span e_2; the copy is q'' = scale q' + offset.              */
+/* Every object splats into its own channel of a count image that           */
+/* ACCUMULATES; splat_xy (nullable) gets [n][t - B - 1][o] positions.       */
+/* ------------------------------------------------------------------------ */
+#define ORC_MAX_OBJECTS 8
+
+typedef struct {
+  int32_t final_kind;          /* ORC_FINAL_IDENTITY, _SWIRL, _STRETCH or _RING */
+  const float *final_params;   /* up to 24 values */
+  float place[6];              /* P row-major (a00 a01 a10 a11), then t */
+  int32_t channel;
+  uint32_t n_copies;           /* 1 = no duplication */
+  float copy_lo[2], copy_span[2];
+  float scale_lo, scale_span;
+} orc_object;
+
+int orc_chaos_scene(const orc_system *s, const orc_object *obj, int n_obj,
+                    const orc_run *r, const orc_window *w, uint32_t *img,
+                    double *splat_xy, uint64_t *dropped) {
+  uint64_t thresh[ORC_MAX_MAPS];
+  int rc = check_common(s, r, w, thresh);
+  if (rc) return rc;
+  if (s->dim != 2 || s->final_kind != ORC_FINAL_IDENTITY || s->compose) return ORC_EINVAL;
+  if (n_obj < 1 || n_obj > ORC_MAX_OBJECTS) return ORC_EINVAL;
+  int any_copies = 0;
+  for (int o = 0; o < n_obj; ++o) {
+    int fk = obj[o].final_kind;
+    if (fk != ORC_FINAL_IDENTITY && fk != ORC_FINAL_SWIRL && fk != ORC_FINAL_STRETCH &&
+        fk != ORC_FINAL_RING)
+      return ORC_EINVAL;
+    if (obj[o].channel < 0 || obj[o].channel >= w->channels) return ORC_EINVAL;
+    if (obj[o].n_copies < 1) return ORC_EINVAL;
+    if (obj[o].n_copies > 1) any_copies = 1;
+  }
+  const uint32_t T = r->n_iters, B = r->burn_in;
+  const size_t plane = (size_t)w->width * (size_t)w->height;
+  const uint32_t key[2] = {(uint32_t)r->seed, (uint32_t)(r->seed >> 32)};
+  uint64_t n_drop = 0;
+  for (uint32_t n = 0; n < r->n_points; ++n) {
+    uint32_t pid = r->point_offset + n;
+    double p[3] = {0, 0, 0};
+    initial_point(r, pid, 2, p);
+    uint32_t words[4] = {0, 0, 0, 0}, cwords[4] = {0, 0, 0, 0};
+    for (uint32_t t = 1; t <= T; ++t) {
+      if ((t - 1) % 4 == 0) {
+        point_stream(r, pid, (t - 1) / 4, 0, words);
+        if (any_copies) point_stream(r, pid, (t - 1) / 4, 2, cwords);
+      }
+      int k = orc_select(words[(t - 1) % 4], thresh, s->n_maps);
+      apply_map(s, k, p);
+      if (t <= B) continue;
+      for (int o = 0; o < n_obj; ++o) {
+        const orc_object *ob = &obj[o];
+        orc_system so = *s;
+        so.final_kind = ob->final_kind;
+        so.final_params = ob->final_params;
+        double g[2], depth = 0.0, q[2];
+        final_transform(&so, p, g, &depth);
+        q[0] = (double)ob->place[0] * g[0] + (double)ob->place[1] * g[1] + (double)ob->place[4];
+        q[1] = (double)ob->place[2] * g[0] + (double)ob->place[3] * g[1] + (double)ob->place[5];
+        if (ob->n_copies > 1) {
+          uint32_t v = (uint32_t)((2u * (uint32_t)o + 1u) * cwords[(t - 1) % 4]);
+          uint32_t c = (uint32_t)(((uint64_t)v * ob->n_copies) >> 32);
+          uint32_t ctr[4] = {c, (uint32_t)o, r->instance, 3u}, cw[4];
+          orc_philox4x32_10(ctr, key, cw);
+          double e0 = ldexp((double)(cw[0] >> 8), -24);
+          double e1 = ldexp((double)(cw[1] >> 8), -24);
+          double e2 = ldexp((double)(cw[2] >> 8), -24);
+          double sc = (double)ob->scale_lo + (double)ob->scale_span * e2;
+          q[0] = sc * q[0] + ((double)ob->copy_lo[0] + (double)ob->copy_span[0] * e0);
+          q[1] = sc * q[1] + ((double)ob->copy_lo[1] + (double)ob->copy_span[1] * e1);
+        }
+        double fx, fy;
+        int ix, iy;
+        int hit = bin_point(w, q, &ix, &iy, &fx, &fy);
+        if (splat_xy) {
+          size_t at = (((size_t)n * (T - B) + (t - B - 1)) * (size_t)n_obj + (size_t)o) * 2;
+          splat_xy[at] = q[0];
+          splat_xy[at + 1] = q[1];
+        }
+        if (hit)
+          img[(size_t)ob->channel * plane + (size_t)iy * w->width + ix] += 1u;
+        else
+          n_drop++;
+      }
+    }
   }
   if (dropped) *dropped += n_drop;
   return ORC_OK;
