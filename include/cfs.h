@@ -78,8 +78,14 @@ enum {
                                  w = p - c twisted about the vertical axis by
                                  kappa w.y, v = M[:, :3] w + M[:, 3],
                                  q = (fx v.x / v.z, fy v.y / v.z), depth v.z */
-  CFS_FINAL_STRETCH = 3       /* 2D, params {sx, sy}: q = (sx x, y - sy cos x)
+  CFS_FINAL_STRETCH = 3,      /* 2D, params {sx, sy}: q = (sx x, y - sy cos x)
                                  (Section 3's stretch is sx = 2, sy = 1) */
+  CFS_FINAL_RING = 4          /* 2D, params {r_in, r_out}: the point at radius
+                                 r about the origin moves along its ray to
+                                 radius sqrt(r_in^2 + (r_out^2 - r_in^2) r^2)
+                                 (the origin to (r_in, 0)): the uniform unit
+                                 disk becomes the uniform annulus, the rings
+                                 of Section 3's multiple-objects scene */
 };
 
 /* Image element types. */
@@ -201,6 +207,50 @@ int cfs_chaos_game(const cfs_system *sys, const cfs_run *run,
 /* Workspace in bytes that cfs_splat needs for this system, run and image. */
 size_t cfs_splat_workspace(const cfs_system *sys, const cfs_run *run,
                            const cfs_image *img, float sigma_px);
+
+/* Several objects from one primitive (Section 3, multiple objects from a
+ * single primitive; fig. "space"): after every step of the chaos game the
+ * point is repositioned once per object and each object's copy is splatted;
+ * the point itself keeps iterating.  An object is a 2D transform
+ * (final_kind IDENTITY, SWIRL, STRETCH or RING with its final_params), then
+ * the placement q' = P q + t (place = a00 a01 a10 a11 t0 t1), then, for
+ * n_copies > 1, duplication: each splat goes to one copy c drawn from the
+ * point's random stream, and copy c is scaled and moved by values that the
+ * random stream of c alone gives, so no copy table exists anywhere:
+ *   draw of iteration t: word (t-1) mod 4 of Philox block
+ *     (point id, (t-1)/4, instance, 2); object o takes
+ *     c = floor(((2o + 1) u mod 2^32) n_copies / 2^32);
+ *   copy c of object o: Philox block (c, o, instance, 3), e_i = (w_i >> 8)
+ *     2^-24; q'' = (scale_lo + scale_span e_2) q' + copy_lo + copy_span e_{0,1}.
+ * Each object splats +1 into channel `channel` of a U32_COUNT image. */
+#define CFS_MAX_OBJECTS 8
+
+typedef struct cfs_object {
+  int32_t final_kind;      /* CFS_FINAL_IDENTITY, _SWIRL, _STRETCH or _RING */
+  float final_params[24];  /* as for cfs_system.final_params */
+  float place[6];          /* P row-major, then t */
+  int32_t channel;         /* 0 .. image channels - 1 */
+  uint32_t n_copies;       /* 1 (no duplication) .. 2^24 */
+  float copy_lo[2];        /* offset of copy c: copy_lo + copy_span e */
+  float copy_span[2];
+  float scale_lo;          /* scale of copy c: scale_lo + scale_span e_2 */
+  float scale_span;
+} cfs_object;
+
+/* Workspace in bytes for cfs_chaos_scene (0 for the direct splat). */
+size_t cfs_chaos_scene_workspace(const cfs_system *sys, const cfs_object *objects,
+                                 int32_t n_objects, const cfs_run *run,
+                                 const cfs_image *img);
+
+/* The chaos game of a 2D primitive (sys: dim 2, final_kind IDENTITY, compose
+ * COPY; affine or circle maps) splatted through n_objects (1..8) objects
+ * into the U32_COUNT image img, which ACCUMULATES; *img->dropped (if given)
+ * counts splats outside the window.  run->precision and run->splat_path as
+ * for cfs_chaos_game; workspace as cfs_chaos_scene_workspace() says (256-byte
+ * aligned). */
+int cfs_chaos_scene(const cfs_system *sys, const cfs_object *objects, int32_t n_objects,
+                    const cfs_run *run, const cfs_image *img, void *workspace,
+                    size_t workspace_bytes, void *stream);
 
 /* Differentiable form, forward (Section 4: automatic generation of the
  * primitive's distribution with autodiff-like tools): the chaos game of a 2D

@@ -19,7 +19,7 @@ CFS_E_DEVICE = -4
 CFS_E_WORKSPACE = -5
 CFS_MAX_MAPS = 64
 
-FINAL_KINDS = {"identity": 0, "swirl": 1, "twist_camera": 2, "stretch": 3}
+FINAL_KINDS = {"identity": 0, "swirl": 1, "twist_camera": 2, "stretch": 3, "ring": 4}
 IMAGE_KINDS = {"u32_count": 0, "f32_density": 1, "u64_depth": 2}
 PRECISIONS = {"f32": 0, "f64": 1}
 MAP_KINDS = {"affine": 0, "circle": 1}
@@ -32,6 +32,7 @@ EXPORTS = (
     "cfs_chaos_game", "cfs_splat_workspace", "cfs_splat", "cfs_splat_backward_workspace",
     "cfs_splat_backward", "cfs_batch_create", "cfs_batch_run", "cfs_batch_update",
     "cfs_batch_plan", "cfs_batch_destroy", "cfs_autotune", "cfs_philox_dump",
+    "cfs_chaos_scene_workspace", "cfs_chaos_scene",
 )
 
 
@@ -55,6 +56,13 @@ class CfsImage(C.Structure):
                 ("channels", C.c_int32), ("lo", C.c_float * 2), ("hi", C.c_float * 2),
                 ("near_plane", C.c_float), ("data", C.c_void_p),
                 ("density", C.c_void_p), ("dropped", C.c_void_p)]
+
+
+class CfsObject(C.Structure):
+    _fields_ = [("final_kind", C.c_int32), ("final_params", C.c_float * 24),
+                ("place", C.c_float * 6), ("channel", C.c_int32), ("n_copies", C.c_uint32),
+                ("copy_lo", C.c_float * 2), ("copy_span", C.c_float * 2),
+                ("scale_lo", C.c_float), ("scale_span", C.c_float)]
 
 
 class CfsBatchItem(C.Structure):
@@ -113,6 +121,11 @@ def load():
     lib.cfs_batch_destroy.restype = None
     lib.cfs_autotune.argtypes = [C.POINTER(CfsBatchItem), C.c_int32, C.POINTER(CfsPlan), P]
     lib.cfs_philox_dump.argtypes = [C.c_uint64, P, P, C.c_uint64, P]
+    lib.cfs_chaos_scene_workspace.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsObject),
+                                              C.c_int32, C.POINTER(CfsRun), C.POINTER(CfsImage)]
+    lib.cfs_chaos_scene_workspace.restype = C.c_size_t
+    lib.cfs_chaos_scene.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsObject), C.c_int32,
+                                    C.POINTER(CfsRun), C.POINTER(CfsImage), P, C.c_size_t, P]
     _lib = lib
     return lib
 

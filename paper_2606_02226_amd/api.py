@@ -160,6 +160,62 @@ def chaos_workspace_bytes(system, run, image, precision="f32", splat_path="auto"
                                             C.byref(image.struct)))
 
 
+def objects_struct(objects):
+    """ctypes array of cfs_object from object dicts (final_kind,
+    final_params, place, channel, n_copies, copy_lo, copy_hi, scale)."""
+    arr = (_lib.CfsObject * len(objects))()
+    for o, ob in zip(arr, objects):
+        o.final_kind = _lib.FINAL_KINDS[ob.get("final_kind", "identity")]
+        fp = np.zeros(24, np.float32)
+        src = np.asarray(ob.get("final_params", ()), np.float32).reshape(-1)
+        fp[: src.size] = src
+        o.final_params = (C.c_float * 24)(*[float(v) for v in fp])
+        pl = np.asarray(ob.get("place", (1, 0, 0, 1, 0, 0)), np.float32)
+        o.place = (C.c_float * 6)(*[float(v) for v in pl])
+        o.channel = int(ob.get("channel", 0))
+        o.n_copies = int(ob.get("n_copies", 1))
+        lo = np.asarray(ob.get("copy_lo", (0, 0)), np.float32)
+        hi = np.asarray(ob.get("copy_hi", (0, 0)), np.float32)
+        o.copy_lo = (C.c_float * 2)(*[float(v) for v in lo])
+        o.copy_span = (C.c_float * 2)(*[float(v) for v in (hi - lo)])
+        sc = np.asarray(ob.get("scale", (1, 1)), np.float32)
+        o.scale_lo = float(sc[0])
+        o.scale_span = float(np.float32(sc[1] - sc[0]))
+    return arr
+
+
+def chaos_scene(system, objects, run, image, *, precision="f32", splat_path="auto",
+                workspace=None, stream=None):
+    """Several objects from one 2D primitive (cfs_chaos_scene) into the
+    u32_count ``image`` (accumulates)."""
+    lib = _lib.load()
+    sysc = system if isinstance(system, System) else System(system)
+    objs = objects_struct(objects)
+    runc = run_struct(run, precision, splat_path)
+    ws_bytes = lib.cfs_chaos_scene_workspace(C.byref(sysc.struct), objs, len(objects),
+                                             C.byref(runc), C.byref(image.struct))
+    ws = None
+    if ws_bytes:
+        if workspace is not None and workspace.numel() >= ws_bytes:
+            ws = workspace
+        else:
+            ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device=image.data.device)
+    rc = lib.cfs_chaos_scene(C.byref(sysc.struct), objs, len(objects), C.byref(runc),
+                             C.byref(image.struct), _ptr(ws), C.c_size_t(ws_bytes),
+                             _stream_handle(stream))
+    check(rc, "cfs_chaos_scene")
+    return image
+
+
+def scene_workspace_bytes(system, objects, run, image, precision="f32", splat_path="auto"):
+    lib = _lib.load()
+    sysc = system if isinstance(system, System) else System(system)
+    runc = run_struct(run, precision, splat_path)
+    return int(lib.cfs_chaos_scene_workspace(C.byref(sysc.struct), objects_struct(objects),
+                                             len(objects), C.byref(runc),
+                                             C.byref(image.struct)))
+
+
 def philox_dump(seed, ctrs, stream=None):
     """Philox4x32-10 blocks of an int32/uint32 device tensor [n][4] of counters."""
     lib = _lib.load()

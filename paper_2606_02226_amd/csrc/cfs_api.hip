@@ -78,6 +78,7 @@ int validate_system(const cfs_system *s) {
     case CFS_FINAL_IDENTITY: break;
     case CFS_FINAL_SWIRL:
     case CFS_FINAL_STRETCH:
+    case CFS_FINAL_RING:
       if (d != 2) return fail(CFS_E_INVALID, "final kind %d needs dim 2", s->final_kind);
       break;
     case CFS_FINAL_TWIST_CAMERA:
@@ -251,10 +252,11 @@ namespace {
 // Points per launch of the binned path: at most 2^24, and few enough that the
 // records of one launch take at most 1 GiB (2^29 16-bit or 2^27 8-byte
 // records), which also keeps record indices within 31 bits.
-uint32_t binned_slice(const cfs_run *run, bool depth) {
+uint32_t binned_slice(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
   const uint64_t slots = depth ? kDSlots : kBinSlots;
   const uint64_t cap = depth ? kDCap : kChunkCap;
-  const uint64_t flushes = (run->n_iters - run->burn_in + slots - 1) / slots;
+  const uint64_t flushes =
+      (static_cast<uint64_t>(run->n_iters - run->burn_in) * per_iter + slots - 1) / slots;
   uint64_t max_blocks = (depth ? (1ull << 27) : (1ull << 29)) / (flushes * cap);
   if (max_blocks < 1) max_blocks = 1;
   uint64_t pts = max_blocks * kBinBlock;
@@ -277,11 +279,106 @@ bool use_binned(const cfs_run *run, const cfs_image *img) {
 
 size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-size_t binned_workspace(const cfs_run *run, const cfs_image *img) {
+size_t binned_workspace(const cfs_run *run, const cfs_image *img, uint32_t per_iter = 1) {
   const uint32_t elems = static_cast<uint32_t>(img->width) * img->height * img->channels;
   const bool depth = img->kind == CFS_IMAGE_U64_DEPTH;
-  const BinPlan bp = bin_plan(binned_slice(run, depth), run->n_iters, run->burn_in, elems, depth);
+  const BinPlan bp = bin_plan(binned_slice(run, depth, per_iter), run->n_iters, run->burn_in,
+                              elems, depth, per_iter);
   return align_up(bp.records_bytes) + 2 * align_up(bp.table_bytes);
+}
+
+// Point the binned arguments of one slice into the workspace.
+void bind_workspace(BinArgs *ba, const BinPlan &bp, void *workspace) {
+  ba->records = static_cast<uint16_t *>(workspace);
+  ba->drecords = static_cast<uint2 *>(workspace);
+  char *tables = static_cast<char *>(workspace) + align_up(bp.records_bytes);
+  ba->chunk_start = reinterpret_cast<uint32_t *>(tables);
+  ba->tile_start = reinterpret_cast<uint32_t *>(tables + align_up(bp.table_bytes));
+  ba->n_chunks = bp.n_chunks;
+  ba->flushes = bp.flushes;
+  ba->n_tiles = bp.n_tiles;
+  ba->elems = bp.elems;
+}
+
+// Scene objects: validation and packing into kernel arguments.
+int validate_objects(const cfs_object *objects, int32_t n_objects, const cfs_image *img) {
+  if (!objects) return fail(CFS_E_INVALID, "objects is NULL");
+  if (n_objects < 1 || n_objects > CFS_MAX_OBJECTS)
+    return fail(CFS_E_INVALID, "n_objects must be in [1, %d] (got %d)", CFS_MAX_OBJECTS,
+                n_objects);
+  for (int o = 0; o < n_objects; ++o) {
+    const cfs_object &ob = objects[o];
+    if (ob.final_kind != CFS_FINAL_IDENTITY && ob.final_kind != CFS_FINAL_SWIRL &&
+        ob.final_kind != CFS_FINAL_STRETCH && ob.final_kind != CFS_FINAL_RING)
+      return fail(CFS_E_INVALID, "object %d: final_kind %d is not a 2D transform", o,
+                  ob.final_kind);
+    for (int i = 0; i < 24; ++i)
+      if (!std::isfinite(ob.final_params[i]))
+        return fail(CFS_E_INVALID, "object %d: final_params[%d] is not finite", o, i);
+    for (int i = 0; i < 6; ++i)
+      if (!std::isfinite(ob.place[i]))
+        return fail(CFS_E_INVALID, "object %d: place[%d] is not finite", o, i);
+    if (!std::isfinite(ob.copy_lo[0]) || !std::isfinite(ob.copy_lo[1]) ||
+        !std::isfinite(ob.copy_span[0]) || !std::isfinite(ob.copy_span[1]) ||
+        !std::isfinite(ob.scale_lo) || !std::isfinite(ob.scale_span))
+      return fail(CFS_E_INVALID, "object %d: copy placement is not finite", o);
+    if (ob.channel < 0 || ob.channel >= img->channels)
+      return fail(CFS_E_INVALID, "object %d: channel %d outside [0, %d)", o, ob.channel,
+                  img->channels);
+    if (ob.n_copies < 1 || ob.n_copies > (1u << 24))
+      return fail(CFS_E_INVALID, "object %d: n_copies must be in [1, 2^24]", o);
+  }
+  return CFS_OK;
+}
+
+SceneArgs pack_objects(const cfs_object *objects, int32_t n_objects) {
+  SceneArgs sc;
+  std::memset(&sc, 0, sizeof sc);
+  sc.n_obj = n_objects;
+  for (int o = 0; o < n_objects; ++o) {
+    const cfs_object &ob = objects[o];
+    SceneObject &d = sc.obj[o];
+    d.kind = ob.final_kind;
+    d.channel = ob.channel;
+    d.n_copies = ob.n_copies;
+    std::memcpy(d.fp, ob.final_params, sizeof d.fp);
+    std::memcpy(d.place, ob.place, sizeof d.place);
+    d.copy_lo[0] = ob.copy_lo[0];
+    d.copy_lo[1] = ob.copy_lo[1];
+    d.copy_span[0] = ob.copy_span[0];
+    d.copy_span[1] = ob.copy_span[1];
+    d.scale_lo = ob.scale_lo;
+    d.scale_span = ob.scale_span;
+    if (ob.n_copies > 1) sc.any_copies = 1;
+  }
+  return sc;
+}
+
+int validate_scene(const cfs_system *sys, const cfs_object *objects, int32_t n_objects,
+                   const cfs_run *run, const cfs_image *img) {
+  int rc = validate_system(sys);
+  if (!rc) rc = validate_run(run);
+  if (!rc) rc = validate_window(img);
+  if (rc) return rc;
+  if (sys->dim != 2) return fail(CFS_E_INVALID, "a scene's primitive must be 2D");
+  if (sys->final_kind != CFS_FINAL_IDENTITY || sys->compose != CFS_COMPOSE_COPY)
+    return fail(CFS_E_INVALID,
+                "a scene's primitive has no transform of its own (the objects carry them)");
+  if (img->kind != CFS_IMAGE_U32_COUNT)
+    return fail(CFS_E_INVALID, "cfs_chaos_scene renders U32_COUNT images");
+  if (run->splat_path < CFS_SPLAT_AUTO || run->splat_path > CFS_SPLAT_BINNED)
+    return fail(CFS_E_INVALID, "unknown splat_path %d", run->splat_path);
+  return validate_objects(objects, n_objects, img);
+}
+
+bool scene_binned(const cfs_run *run, const cfs_image *img, int32_t n_objects) {
+  if (run->splat_path == CFS_SPLAT_DIRECT) return false;
+  if (run->n_iters == run->burn_in || run->n_points == 0) return false;
+  const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
+  if (elems > static_cast<uint64_t>(kMaxTiles) * kTileElems) return false;
+  if (run->splat_path == CFS_SPLAT_BINNED) return true;
+  return static_cast<uint64_t>(run->n_points) * (run->n_iters - run->burn_in) * n_objects >=
+         (1ull << 20);
 }
 
 }  // namespace
@@ -373,16 +470,63 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
       sj.out.final_points = static_cast<char *>(final_points) + static_cast<size_t>(done) * sys->dim * real_bytes;
     if (last_index) sj.out.last_index = last_index + done;
     if (indices) sj.out.indices = indices + static_cast<size_t>(done) * run->n_iters;
-    sj.ba.records = static_cast<uint16_t *>(workspace);
-    sj.ba.drecords = static_cast<uint2 *>(workspace);
-    char *tables = static_cast<char *>(workspace) + align_up(bp.records_bytes);
-    sj.ba.chunk_start = reinterpret_cast<uint32_t *>(tables);
-    sj.ba.tile_start = reinterpret_cast<uint32_t *>(tables + align_up(bp.table_bytes));
-    sj.ba.n_chunks = bp.n_chunks;
-    sj.ba.flushes = bp.flushes;
-    sj.ba.n_tiles = bp.n_tiles;
-    sj.ba.elems = bp.elems;
+    bind_workspace(&sj.ba, bp, workspace);
     rc = device_status(launch_chaos_binned(sj, s), "cfs_chaos_game");
+    if (rc) return rc;
+  }
+  return CFS_OK;
+}
+
+extern "C" size_t cfs_chaos_scene_workspace(const cfs_system *sys, const cfs_object *objects,
+                                            int32_t n_objects, const cfs_run *run,
+                                            const cfs_image *img) {
+  if (validate_scene(sys, objects, n_objects, run, img)) return 0;
+  if (!scene_binned(run, img, n_objects)) return 0;
+  return binned_workspace(run, img, static_cast<uint32_t>(n_objects));
+}
+
+extern "C" int cfs_chaos_scene(const cfs_system *sys, const cfs_object *objects,
+                               int32_t n_objects, const cfs_run *run, const cfs_image *img,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+  clear_error();
+  int rc = validate_scene(sys, objects, n_objects, run, img);
+  if (rc) return rc;
+  const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
+  if (run->splat_path == CFS_SPLAT_BINNED && elems > static_cast<uint64_t>(kMaxTiles) * kTileElems)
+    return fail(CFS_E_UNSUPPORTED, "binned splat handles images of at most %u elements",
+                static_cast<unsigned>(kMaxTiles * kTileElems));
+  SceneJob job;
+  std::memset(&job, 0, sizeof job);
+  job.precision = run->precision;
+  job.binned = scene_binned(run, img, n_objects);
+  const uint32_t per_iter = static_cast<uint32_t>(n_objects);
+  if (job.binned) {
+    const size_t need = binned_workspace(run, img, per_iter);
+    if (!workspace || workspace_bytes < need)
+      return fail(CFS_E_WORKSPACE, "binned splat needs %zu bytes of workspace, got %zu", need,
+                  workspace ? workspace_bytes : static_cast<size_t>(0));
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+      return fail(CFS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  }
+  rc = pack_table<2>(sys, &job.mt, &job.equal);
+  if (rc) return rc;
+  job.win = make_window(img, false);
+  job.ra = make_run_args(run);
+  job.sc = pack_objects(objects, n_objects);
+  job.img = static_cast<uint32_t *>(img->data);
+  job.dropped = img->dropped;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!job.binned) return device_status(launch_scene(job, s), "cfs_chaos_scene");
+  const uint32_t slice = binned_slice(run, false, per_iter);
+  for (uint32_t done = 0; done < run->n_points; done += slice) {
+    const uint32_t pts = std::min(slice, run->n_points - done);
+    const BinPlan bp = bin_plan(pts, run->n_iters, run->burn_in, static_cast<uint32_t>(elems),
+                                false, per_iter);
+    SceneJob sj = job;
+    sj.ra.n_points = pts;
+    sj.ra.point_offset = run->point_offset + done;
+    bind_workspace(&sj.ba, bp, workspace);
+    rc = device_status(launch_scene(sj, s), "cfs_chaos_scene");
     if (rc) return rc;
   }
   return CFS_OK;

@@ -194,6 +194,18 @@ __device__ __forceinline__ void final_transform(const float *__restrict__ fp, co
   } else if constexpr (FINAL == kFinalStretch) {
     q[0] = static_cast<real>(fp[0]) * p[0];
     q[1] = p[1] - static_cast<real>(fp[1]) * cos_r(p[0]);
+  } else if constexpr (FINAL == kFinalRing) {
+    const real ri = fp[0], ro = fp[1];
+    const real r2 = p[0] * p[0] + p[1] * p[1];
+    const real R = sqrt_r(ri * ri + (ro * ro - ri * ri) * r2);
+    if (r2 > static_cast<real>(0)) {
+      const real r = sqrt_r(r2);
+      q[0] = R * (p[0] / r);
+      q[1] = R * (p[1] / r);
+    } else {
+      q[0] = R;
+      q[1] = static_cast<real>(0);
+    }
   } else if constexpr (FINAL == kFinalTwistCamera) {
     const real wx = p[0] - static_cast<real>(fp[1]);
     const real wy = p[1] - static_cast<real>(fp[2]);

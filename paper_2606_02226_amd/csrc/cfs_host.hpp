@@ -36,10 +36,27 @@ struct BinPlan {
   uint32_t blocks, flushes, n_chunks, n_tiles, elems;
   size_t records_bytes, table_bytes;
 };
+// per_iter: records a lane stages per step after burn-in (objects of a scene).
 BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems,
-                 bool depth = false);
+                 bool depth = false, uint32_t per_iter = 1);
 
 hipError_t launch_chaos_binned(const ChaosJob &job, hipStream_t stream);
+// Transpose the run table and add the binned count records into img.
+hipError_t launch_count_accumulate(const BinArgs &ba, uint32_t *img, hipStream_t stream);
+
+struct SceneJob {
+  int precision;
+  bool equal;
+  bool binned;
+  MapTable<2> mt;
+  Window win;
+  RunArgs ra;
+  SceneArgs sc;
+  uint32_t *img;
+  unsigned long long *dropped;
+  BinArgs ba;
+};
+hipError_t launch_scene(const SceneJob &job, hipStream_t stream);
 hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,
                             hipStream_t stream);
 

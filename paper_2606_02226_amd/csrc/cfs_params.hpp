@@ -12,6 +12,7 @@ constexpr int kFinalIdentity = 0;
 constexpr int kFinalSwirl = 1;
 constexpr int kFinalTwistCamera = 2;
 constexpr int kFinalStretch = 3;
+constexpr int kFinalRing = 4;
 
 // Map table of one system: per map A row-major then b (dim*(dim+1) floats),
 // and the finite selection thresholds.  n_search == 0 selects with equal
@@ -114,6 +115,25 @@ struct GaussCkpt {
   float *ckpt;           // [n_ckpt][stride][2] (base already offset to the slice)
   int32_t every;
   uint32_t stride;       // points of the whole run
+};
+
+// Objects of a scene (several objects from one primitive): transform kind
+// and its first 8 parameters, placement, channel and duplication.
+constexpr int kMaxObjects = 8;
+struct SceneObject {
+  int32_t kind;
+  int32_t channel;
+  uint32_t n_copies;
+  int32_t pad;
+  float fp[8];
+  float place[6];
+  float copy_lo[2], copy_span[2];
+  float scale_lo, scale_span;
+};
+struct SceneArgs {
+  SceneObject obj[kMaxObjects];
+  int32_t n_obj;
+  int32_t any_copies;
 };
 
 struct Outputs {

@@ -87,11 +87,12 @@ hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, ui
   return hipGetLastError();
 }
 
-BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems, bool depth) {
+BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems, bool depth,
+                 uint32_t per_iter) {
   BinPlan bp{};
   const uint32_t slots = depth ? kDSlots : kBinSlots;
   bp.blocks = (points + kBinBlock - 1) / kBinBlock;
-  bp.flushes = (n_iters - burn_in + slots - 1) / slots;
+  bp.flushes = ((n_iters - burn_in) * per_iter + slots - 1) / slots;
   bp.n_chunks = bp.blocks * bp.flushes;
   bp.n_tiles = depth ? (elems + kDTileElems - 1) / kDTileElems : (elems + kTileElems - 1) / kTileElems;
   bp.elems = elems;
@@ -99,6 +100,14 @@ BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t e
                            : static_cast<size_t>(bp.n_chunks) * kChunkCap * sizeof(uint16_t);
   bp.table_bytes = static_cast<size_t>(bp.n_tiles + 1) * bp.n_chunks * sizeof(uint32_t);  // each of two
   return bp;
+}
+
+hipError_t launch_count_accumulate(const BinArgs &ba, uint32_t *img, hipStream_t s) {
+  hipError_t e = launch_transpose(ba.chunk_start, ba.tile_start, ba.n_chunks, ba.n_tiles + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tile_accumulate, dim3(ba.n_tiles), dim3(kAccBlock), 0, s, ba.records,
+                     ba.tile_start, ba.n_chunks, ba.elems, img);
+  return hipGetLastError();
 }
 
 template <typename real, int DIM, int FINAL, bool EQUAL>
@@ -111,11 +120,7 @@ static hipError_t launch_binned_typed(const ChaosJob &j, hipStream_t s) {
                      s, mt, j.win, j.ra, j.fa, j.ba, j.out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || j.ba.n_chunks == 0) return e;
-  e = launch_transpose(j.ba.chunk_start, j.ba.tile_start, j.ba.n_chunks, j.ba.n_tiles + 1, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tile_accumulate, dim3(j.ba.n_tiles), dim3(kAccBlock), 0, s, j.ba.records,
-                     j.ba.tile_start, j.ba.n_chunks, j.ba.elems, static_cast<uint32_t *>(j.img));
-  return hipGetLastError();
+  return launch_count_accumulate(j.ba, static_cast<uint32_t *>(j.img), s);
 }
 
 template <typename real, int DIM, int FINAL>
@@ -130,6 +135,7 @@ static hipError_t launch_binned_real(const ChaosJob &j, hipStream_t s) {
   switch (j.final_kind) {
     case kFinalSwirl: return launch_binned_sel<real, 2, kFinalSwirl>(j, s);
     case kFinalStretch: return launch_binned_sel<real, 2, kFinalStretch>(j, s);
+    case kFinalRing: return launch_binned_sel<real, 2, kFinalRing>(j, s);
     default: return launch_binned_sel<real, 2, kFinalIdentity>(j, s);
   }
 }

@@ -51,6 +51,7 @@ static hipError_t launch_real(const ChaosJob &j, hipStream_t s) {
     switch (j.final_kind) {
       case kFinalSwirl: return launch_sel<real, 2, kFinalSwirl, false>(j, s);
       case kFinalStretch: return launch_sel<real, 2, kFinalStretch, false>(j, s);
+      case kFinalRing: return launch_sel<real, 2, kFinalRing, false>(j, s);
       default: return launch_sel<real, 2, kFinalIdentity, false>(j, s);
     }
   }

@@ -239,3 +239,64 @@ def test_bad_compose(L):
     s3.compose = 1
     assert _call(L, s3, _run(L), _image(L)) == L.CFS_E_INVALID
     assert "dim 2" in lib.cfs_last_error().decode()
+
+
+def _objects(L, n=1, **kw):
+    arr = (L.CfsObject * max(n, 1))()
+    for o in arr:
+        o.place = (C.c_float * 6)(1, 0, 0, 1, 0, 0)
+        o.n_copies = 1
+        for k, v in kw.items():
+            setattr(o, k, v)
+    return arr
+
+
+def _scene_call(L, s, objs, n, r=None, img=None):
+    lib = L.load()
+    r = r or _run(L)
+    img = img or _image(L)
+    img.data = PLACEHOLDER
+    return lib.cfs_chaos_scene(C.byref(s), objs, n, C.byref(r), C.byref(img), None, 0, None)
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("n0", "n_objects"), ("n9", "n_objects"), ("channel", "channel"), ("kind", "2D transform"),
+    ("copies", "n_copies"), ("place", "place"), ("primitive", "no transform"),
+    ("dim3", "2D"), ("null", "objects is NULL"), ("depth_image", "density buffer"),
+])
+def test_scene_validation(L, case, msg):
+    lib = L.load()
+    s, keep = _system(L, n=3)
+    objs, n = _objects(L, 1), 1
+    img = None
+    if case == "n0":
+        n = 0
+    elif case == "n9":
+        objs, n = _objects(L, 9), 9
+    elif case == "channel":
+        objs = _objects(L, 1, channel=1)
+    elif case == "kind":
+        objs = _objects(L, 1, final_kind=2)
+    elif case == "copies":
+        objs = _objects(L, 1, n_copies=0)
+    elif case == "place":
+        objs = _objects(L, 1)
+        objs[0].place[4] = float("nan")
+    elif case == "primitive":
+        s.final_kind = 1
+    elif case == "dim3":
+        s, keep = _system(L, dim=3, n=3)
+    elif case == "null":
+        objs = None
+    elif case == "depth_image":
+        img = _image(L, kind=2)
+    assert _scene_call(L, s, objs, n, img=img) == L.CFS_E_INVALID
+    assert msg in lib.cfs_last_error().decode()
+
+
+def test_scene_workspace_zero_on_invalid(L):
+    lib = L.load()
+    s, keep = _system(L, n=3)
+    objs = _objects(L, 1, channel=5)
+    assert lib.cfs_chaos_scene_workspace(C.byref(s), objs, 1, C.byref(_run(L)),
+                                         C.byref(_image(L))) == 0
