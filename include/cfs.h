@@ -291,6 +291,21 @@ int cfs_splat_backward(const cfs_system *sys, const cfs_run *run,
                        int32_t ckpt_every, float *grad, void *workspace,
                        size_t workspace_bytes, void *stream);
 
+/* Workspace in bytes for cfs_l2_loss over n elements. */
+size_t cfs_l2_loss_workspace(uint64_t n);
+
+/* Image loss of the fitting loop (Section 4: fitting a primitive's
+ * distribution with autodiff-like tools): with D = density and D* = target
+ * (device float [n] each),
+ *   *loss  = sum_i (D_i - D*_i)^2     (device double, FP64 sum), and
+ *   dL_dD_i = 2 (D_i - D*_i)          (device float [n], nullable),
+ * the upstream gradient that cfs_splat_backward takes.  The reduction has a
+ * fixed order for a given n, so the loss is bit-reproducible.  workspace:
+ * device, cfs_l2_loss_workspace(n) bytes, 8-byte aligned; loss 8-byte
+ * aligned. */
+int cfs_l2_loss(const float *density, const float *target, uint64_t n, float *dL_dD,
+                double *loss, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Batched form: many heterogeneous systems (animation frames, different map
  * counts, point counts and image sizes) rendered by persistent kernels inside
  * ONE HIP graph launch (abstract and Section 4 of the paper: animation).  Each

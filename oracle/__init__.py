@@ -325,6 +325,13 @@ def splat_gauss_backward(system, run, image, sigma_px, dL_dD):
     return grad
 
 
+def l2_loss(density, target):
+    """The fitting loop's image loss (Section 4): sum (D - D*)^2 in FP64 and
+    its gradient 2 (D - D*), both from the float inputs widened exactly."""
+    d = np.asarray(density, np.float64).reshape(-1) - np.asarray(target, np.float64).reshape(-1)
+    return float(np.dot(d, d)), 2.0 * d
+
+
 def gauss_loss(system, run, image, sigma_px, target):
     """L = sum (D - D*)^2 with D from splat_gauss."""
     D = splat_gauss(system, run, image, sigma_px)

@@ -32,7 +32,7 @@ EXPORTS = (
     "cfs_chaos_game", "cfs_splat_workspace", "cfs_splat", "cfs_splat_backward_workspace",
     "cfs_splat_backward", "cfs_batch_create", "cfs_batch_run", "cfs_batch_update",
     "cfs_batch_plan", "cfs_batch_destroy", "cfs_autotune", "cfs_philox_dump",
-    "cfs_chaos_scene_workspace", "cfs_chaos_scene",
+    "cfs_chaos_scene_workspace", "cfs_chaos_scene", "cfs_l2_loss_workspace", "cfs_l2_loss",
 )
 
 
@@ -121,6 +121,9 @@ def load():
     lib.cfs_batch_destroy.restype = None
     lib.cfs_autotune.argtypes = [C.POINTER(CfsBatchItem), C.c_int32, C.POINTER(CfsPlan), P]
     lib.cfs_philox_dump.argtypes = [C.c_uint64, P, P, C.c_uint64, P]
+    lib.cfs_l2_loss_workspace.argtypes = [C.c_uint64]
+    lib.cfs_l2_loss_workspace.restype = C.c_size_t
+    lib.cfs_l2_loss.argtypes = [P, P, C.c_uint64, P, P, P, C.c_size_t, P]
     lib.cfs_chaos_scene_workspace.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsObject),
                                               C.c_int32, C.POINTER(CfsRun), C.POINTER(CfsImage)]
     lib.cfs_chaos_scene_workspace.restype = C.c_size_t

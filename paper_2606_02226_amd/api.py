@@ -276,6 +276,29 @@ def splat_backward(system, run, image, sigma_px, dL_dD, ckpt, ckpt_every=8, grad
     return grad
 
 
+def l2_loss(density, target, *, grad=None, want_grad=True, workspace=None, stream=None):
+    """cfs_l2_loss: returns (loss as a float64 device tensor [1], dL/dD or
+    None).  ``density`` and ``target`` are float32 device tensors of equal
+    size; ``grad`` (float32, same size) is written when given or when
+    ``want_grad``."""
+    lib = _lib.load()
+    d = density.contiguous()
+    t = target.contiguous()
+    if d.dtype != torch.float32 or t.dtype != torch.float32 or d.numel() != t.numel():
+        raise ValueError("density and target must be float32 tensors of equal size")
+    n = d.numel()
+    if grad is None and want_grad:
+        grad = torch.empty_like(d)
+    loss = torch.empty(1, dtype=torch.float64, device=d.device)
+    ws_bytes = int(lib.cfs_l2_loss_workspace(C.c_uint64(n)))
+    if workspace is None or workspace.numel() * workspace.element_size() < ws_bytes:
+        workspace = torch.empty((ws_bytes + 7) // 8, dtype=torch.float64, device=d.device)
+    check(lib.cfs_l2_loss(_ptr(d), _ptr(t), C.c_uint64(n), _ptr(grad), _ptr(loss),
+                          _ptr(workspace), C.c_size_t(ws_bytes), _stream_handle(stream)),
+          "cfs_l2_loss")
+    return loss, grad
+
+
 def theta_to_system(theta, like=None, prob=None):
     """System dict of a 2D affine IFS from parameters [n][6] =
     (a00, a01, a10, a11, b0, b1) (a host copy is taken: the map table travels

@@ -171,3 +171,25 @@ extern "C" int cfs_splat_backward(const cfs_system *sys, const cfs_run *run, con
   return device_status(launch_splat_backward(job, static_cast<hipStream_t>(stream)),
                        "cfs_splat_backward");
 }
+
+extern "C" size_t cfs_l2_loss_workspace(uint64_t n) {
+  return static_cast<size_t>(loss_blocks(n)) * sizeof(double);
+}
+
+extern "C" int cfs_l2_loss(const float *density, const float *target, uint64_t n, float *dL_dD,
+                           double *loss, void *workspace, size_t workspace_bytes, void *stream) {
+  clear_error();
+  if (!loss) return fail(CFS_E_INVALID, "loss is NULL");
+  if (n && (!density || !target)) return fail(CFS_E_INVALID, "density/target is NULL");
+  if (n > (1ull << 40)) return fail(CFS_E_INVALID, "n exceeds 2^40");
+  const size_t need = cfs_l2_loss_workspace(n);
+  if (!workspace || workspace_bytes < need)
+    return fail(CFS_E_WORKSPACE, "cfs_l2_loss needs %zu bytes of workspace, got %zu", need,
+                workspace ? workspace_bytes : static_cast<size_t>(0));
+  if (reinterpret_cast<uintptr_t>(workspace) % 8 || reinterpret_cast<uintptr_t>(loss) % 8)
+    return fail(CFS_E_INVALID, "workspace and loss must be 8-byte aligned");
+  return device_status(launch_l2_loss(density, target, n, dL_dD, loss,
+                                      static_cast<double *>(workspace),
+                                      static_cast<hipStream_t>(stream)),
+                       "cfs_l2_loss");
+}

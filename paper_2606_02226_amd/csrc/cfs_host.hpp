@@ -84,6 +84,9 @@ hipError_t launch_splat_forward(const GaussJob &job, hipStream_t stream);
 hipError_t launch_splat_backward(const GaussJob &job, hipStream_t stream);
 
 hipError_t launch_chaos(const ChaosJob &job, hipStream_t stream);
+uint32_t loss_blocks(uint64_t n);
+hipError_t launch_l2_loss(const float *d, const float *target, uint64_t n, float *grad,
+                          double *loss, double *partial, hipStream_t stream);
 hipError_t launch_clear_u32(uint32_t *p, size_t n, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v,
                            hipStream_t stream);

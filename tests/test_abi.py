@@ -300,3 +300,14 @@ def test_scene_workspace_zero_on_invalid(L):
     objs = _objects(L, 1, channel=5)
     assert lib.cfs_chaos_scene_workspace(C.byref(s), objs, 1, C.byref(_run(L)),
                                          C.byref(_image(L))) == 0
+
+
+def test_l2_loss_validation(L):
+    lib = L.load()
+    assert lib.cfs_l2_loss_workspace(0) == 8
+    assert lib.cfs_l2_loss_workspace(10**9) == 1024 * 8
+    assert lib.cfs_l2_loss(None, None, 0, None, None, None, 0, None) == L.CFS_E_INVALID
+    assert "loss is NULL" in lib.cfs_last_error().decode()
+    assert lib.cfs_l2_loss(None, None, 5, None, PLACEHOLDER, None, 0, None) == L.CFS_E_INVALID
+    assert lib.cfs_l2_loss(PLACEHOLDER, PLACEHOLDER, 5, None, PLACEHOLDER, None, 0,
+                           None) == L.CFS_E_WORKSPACE
