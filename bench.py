@@ -163,6 +163,28 @@ def forms(dev, precision):
         "checkpoint_bytes": int(ckpt.numel() * 4),
         "full_trajectory_bytes": int(N * (T + 1) * 2 * 4),
         "error": "gradient within 1e-4 rel. L2 of the FP64 adjoint and 1e-3 of FD (tests)"}
+    del ckpt, img, cimg
+    # several objects from one primitive: the 1920x1080 four-object scene
+    w = workloads.space_scene()
+    simg = api.Image(w["image"], device=dev)
+    sws = torch.empty(api.scene_workspace_bytes(w["system"], w["objects"], w["run"], simg,
+                                                precision), dtype=torch.uint8, device=dev)
+    sys_s = api.System(w["system"])
+
+    def scene():
+        simg.clear()
+        api.chaos_scene(sys_s, w["objects"], w["run"], simg, precision=precision, workspace=sws)
+
+    scene_ms = _timed(scene, 10, stream)
+    N, T, B = w["run"]["n_points"], w["run"]["n_iters"], w["run"]["burn_in"]
+    n_obj = len(w["objects"])
+    out["scene"] = {
+        "workload": "circle IFS primitive, 4 objects (planet, rings, 512 stars, comet), "
+                    "2^22 points x 32 iterations (8 burn-in), 4 x 1920x1080 u32",
+        "precision": precision, "frame_ms": scene_ms,
+        "point_iterations_per_s": N * T / (scene_ms * 1e-3),
+        "splats_per_s": N * (T - B) * n_obj / (scene_ms * 1e-3),
+        "error": "FP64: within 1e-4 rel. L1 of the oracle; direct and binned bit-identical (tests)"}
     return out
 
 

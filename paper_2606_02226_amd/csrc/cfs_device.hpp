@@ -226,6 +226,17 @@ __device__ __forceinline__ void final_transform(const float *__restrict__ fp, co
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b to XCD
+// b mod 8) and every XCD has an L2 of its own.  Kernels whose neighbouring
+// items share cache lines of their input (the runs of adjacent image tiles
+// are adjacent in every chunk of records) take item xcd_item(b, n) instead of
+// b: XCD x then works through one contiguous range of the n items.  A
+// bijection of [0, n) for every n.
+__device__ __forceinline__ uint32_t xcd_item(uint32_t b, uint32_t n) {
+  const uint32_t x = b & 7u, j = b >> 3, q = n >> 3, r = n & 7u;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // Pixel of q in the window, or -1 when it is dropped (outside or NaN).
 template <typename real>
 __device__ __forceinline__ int bin_pixel(const real q[2], const Window &w, int *ix_out) {

@@ -60,7 +60,8 @@ __global__ __launch_bounds__(kDAccBlock) void k_depth_accumulate(const uint2 *__
                                                                  uint32_t *density) {
   __shared__ unsigned long long keys[kDTileElems];
   __shared__ uint32_t counts[kDTileElems];
-  depth_tile_accumulate(rec, tile_start, n_chunks, elems, img, density, blockIdx.x, keys, counts);
+  depth_tile_accumulate(rec, tile_start, n_chunks, elems, img, density,
+                        xcd_item(blockIdx.x, gridDim.x), keys, counts);
 }
 
 // One workgroup per image tile.
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kAccBlock) void k_tile_accumulate(const uint16_t *_
                                                                uint32_t n_chunks, uint32_t elems,
                                                                uint32_t *__restrict__ img) {
   __shared__ uint32_t tile[kTileElems];
-  tile_accumulate(rec, tile_start, n_chunks, elems, img, blockIdx.x, tile);
+  tile_accumulate(rec, tile_start, n_chunks, elems, img, xcd_item(blockIdx.x, gridDim.x), tile);
 }
 
 __global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ in,

@@ -202,7 +202,8 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
                                                                  float *__restrict__ dens) {
   __shared__ float acc[kGTile * kGTile];
   const int tid = threadIdx.x;
-  const int tx = blockIdx.x % gp.tiles_x, ty = blockIdx.x / gp.tiles_x;
+  const uint32_t t = xcd_item(blockIdx.x, gridDim.x);
+  const int tx = t % gp.tiles_x, ty = t / gp.tiles_x;
   const int x0 = tx * kGTile, y0 = ty * kGTile;
   const int xlo = x0, xhi = min(x0 + kGTile, gp.width);
   const int ylo = y0, yhi = min(y0 + kGTile, gp.height);
