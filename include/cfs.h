@@ -313,7 +313,8 @@ int cfs_l2_loss(const float *density, const float *target, uint64_t n, float *dL
  * streams, same device functions, FP32 or FP64 positions per instance), so
  * its image is bit-identical to the plain call's. */
 typedef struct cfs_batch_item {
-  cfs_system sys;  /* 2D, identity transform, up to CFS_MAX_MAPS maps */
+  cfs_system sys;  /* 2D, affine maps, identity transform, up to CFS_MAX_MAPS
+                      maps */
   cfs_run run;     /* run.instance selects the instance's random streams;
                       splat_path is ignored (the plan decides) */
   cfs_image img;   /* CFS_IMAGE_U32_COUNT, 1 or n_maps channels, caller-owned

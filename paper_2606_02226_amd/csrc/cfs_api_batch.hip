@@ -57,6 +57,10 @@ int validate_item(const cfs_batch_item &it, int i) {
   if (rc) return fail(rc, "batch item %d: %s", i, cfs_last_error());
   if (it.sys.dim != 2 || it.sys.final_kind != CFS_FINAL_IDENTITY)
     return fail(CFS_E_UNSUPPORTED, "batch item %d: 2D systems with the identity transform only", i);
+  if (it.sys.kind)
+    for (int m = 0; m < it.sys.n_maps; ++m)
+      if (it.sys.kind[m] != CFS_MAP_AFFINE)
+        return fail(CFS_E_UNSUPPORTED, "batch item %d: affine maps only", i);
   if (it.img.kind != CFS_IMAGE_U32_COUNT ||
       (it.img.channels != 1 && it.img.channels != it.sys.n_maps))
     return fail(CFS_E_INVALID, "batch item %d: U32_COUNT image with 1 or n_maps channels", i);
@@ -264,6 +268,9 @@ extern "C" int cfs_batch_update(cfs_batch *b, int32_t index, const cfs_system *s
   if (rc) return rc;
   if (sys->dim != 2 || sys->final_kind != CFS_FINAL_IDENTITY)
     return fail(CFS_E_UNSUPPORTED, "2D systems with the identity transform only");
+  if (sys->kind)
+    for (int m = 0; m < sys->n_maps; ++m)
+      if (sys->kind[m] != CFS_MAP_AFFINE) return fail(CFS_E_UNSUPPORTED, "affine maps only");
   if (sys->n_maps != b->n_maps[index])
     return fail(CFS_E_INVALID, "instance %d has %d maps, the update has %d", index, b->n_maps[index],
                 sys->n_maps);

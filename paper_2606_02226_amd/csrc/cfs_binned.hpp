@@ -91,12 +91,16 @@ __device__ inline void flush_chunk(uint32_t *stage, uint32_t *cnt, uint32_t *wsu
 // One block of kBinBlock points (block index `block` of the run): the chaos
 // game of each lane's point with the binned splat.  table/th hold the map
 // table in LDS; cnt[0 .. n_tiles) must be zero on entry and is zero on exit.
-// Every thread of the workgroup calls it (it holds barriers).
-template <typename real, int DIM, int FINAL, int SEL>
+// Every thread of the workgroup calls it (it holds barriers).  GENERAL
+// compiles the circle-map and reuse branches (`flags`); without it they are
+// compiled out, which keeps the affine copy-transform loop at its register
+// count.
+template <typename real, int DIM, int FINAL, int SEL, bool GENERAL = true>
 __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_maps, int n_search,
                                    int top_step, int flags, const Window &win, const RunArgs &ra,
                                    const float *fparams, const BinArgs &ba, const Outputs &out,
                                    uint32_t block, uint32_t *stage, uint32_t *cnt, uint32_t *wsum) {
+  if constexpr (!GENERAL) flags = 0;
   const int tid = threadIdx.x;
   const uint32_t n = block * kBinBlock + tid;
   const bool active = n < ra.n_points;

@@ -8,11 +8,13 @@ namespace cfs {
 
 // The chaos game of point n of a run with the direct splat (one device
 // atomic per splat).  table/th hold the map table in LDS.
-template <typename real, int DIM, int FINAL, int SEL, bool DEPTH>
+// GENERAL as for chaos_binned_block.
+template <typename real, int DIM, int FINAL, int SEL, bool DEPTH, bool GENERAL = true>
 __device__ void chaos_direct_point(const real *table, const uint32_t *th, int n_maps, int n_search,
                                    int top_step, int flags, const Window &win, const RunArgs &ra,
                                    const float *fparams, void *img, uint32_t *density,
                                    float near_plane, const Outputs &out, uint32_t n) {
+  if constexpr (!GENERAL) flags = 0;
   if (n >= ra.n_points) return;
   const uint32_t pid = ra.point_offset + n;
   const uint32_t T = ra.n_iters, B = ra.burn_in;

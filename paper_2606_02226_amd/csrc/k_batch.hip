@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_emit(const InstDesc *__rest
     ba.elems = d.elems;
     Outputs out{nullptr, nullptr, nullptr, d.dropped};
     for (uint32_t b = 0; b < item.n_blocks; ++b)
-      chaos_binned_block<real, 2, kFinalIdentity, kSelRuntime>(
+      chaos_binned_block<real, 2, kFinalIdentity, kSelRuntime, false>(
           table, th, d.mt.n_maps, d.mt.n_search, d.mt.top_step, d.mt.flags, d.win, d.ra, nullptr,
           ba, out,
           item.first_block + b, stage, cnt, wsum);
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_direct(const InstDesc *__re
     __syncthreads();
     Outputs out{nullptr, nullptr, nullptr, d.dropped};
     for (uint32_t b = 0; b < item.n_blocks; ++b)
-      chaos_direct_point<real, 2, kFinalIdentity, kSelRuntime, false>(
+      chaos_direct_point<real, 2, kFinalIdentity, kSelRuntime, false, false>(
           table, th, d.mt.n_maps, d.mt.n_search, d.mt.top_step, d.mt.flags, d.win, d.ra, nullptr,
           d.img,
           nullptr, 0.0f, out, (item.first_block + b) * kBinBlock + threadIdx.x);

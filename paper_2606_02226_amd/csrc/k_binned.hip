@@ -18,7 +18,7 @@
 
 namespace cfs {
 
-template <typename real, int DIM, int FINAL, bool EQUAL>
+template <typename real, int DIM, int FINAL, bool EQUAL, bool GENERAL>
 __global__ __launch_bounds__(kBinBlock) void k_chaos_binned(MapTable<DIM> mt, Window win,
                                                             RunArgs ra, FinalArgs fa, BinArgs ba,
                                                             Outputs out) {
@@ -30,9 +30,9 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_binned(MapTable<DIM> mt, Wi
   load_table<real, DIM>(mt, table, th);
   for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
   __syncthreads();
-  chaos_binned_block<real, DIM, FINAL, EQUAL>(table, th, mt.n_maps, mt.n_search, mt.top_step,
-                                              mt.flags, win, ra, fa.p, ba, out, blockIdx.x, stage,
-                                              cnt, wsum);
+  chaos_binned_block<real, DIM, FINAL, EQUAL, GENERAL>(table, th, mt.n_maps, mt.n_search,
+                                                       mt.top_step, mt.flags, win, ra, fa.p, ba,
+                                                       out, blockIdx.x, stage, cnt, wsum);
 }
 
 template <typename real, bool EQUAL>
@@ -117,8 +117,13 @@ static hipError_t launch_binned_typed(const ChaosJob &j, hipStream_t s) {
     if constexpr (DIM == 2) return j.mt2; else return j.mt3;
   }();
   const uint32_t blocks = (j.ra.n_points + kBinBlock - 1) / kBinBlock;
-  hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL>), dim3(blocks), dim3(kBinBlock), 0,
-                     s, mt, j.win, j.ra, j.fa, j.ba, j.out);
+  // circle maps and reuse composition are 2D only
+  if (DIM == 2 && mt.flags != 0)
+    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, DIM == 2>), dim3(blocks),
+                       dim3(kBinBlock), 0, s, mt, j.win, j.ra, j.fa, j.ba, j.out);
+  else
+    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, false>), dim3(blocks),
+                       dim3(kBinBlock), 0, s, mt, j.win, j.ra, j.fa, j.ba, j.out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || j.ba.n_chunks == 0) return e;
   return launch_count_accumulate(j.ba, static_cast<uint32_t *>(j.img), s);

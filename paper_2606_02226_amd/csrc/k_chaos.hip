@@ -13,7 +13,7 @@ namespace cfs {
 
 constexpr int kChaosBlock = 256;
 
-template <typename real, int DIM, int FINAL, bool EQUAL, bool DEPTH>
+template <typename real, int DIM, int FINAL, bool EQUAL, bool DEPTH, bool GENERAL>
 __global__ __launch_bounds__(kChaosBlock) void k_chaos(MapTable<DIM> mt, Window win,
                                                        RunArgs ra, FinalArgs fa, void *img,
                                                        uint32_t *density, float near_plane,
@@ -22,10 +22,9 @@ __global__ __launch_bounds__(kChaosBlock) void k_chaos(MapTable<DIM> mt, Window 
   __shared__ uint32_t th[kMaxMaps];
   load_table<real, DIM>(mt, table, th);
   __syncthreads();
-  chaos_direct_point<real, DIM, FINAL, EQUAL, DEPTH>(table, th, mt.n_maps, mt.n_search, mt.top_step,
-                                                     mt.flags, win, ra, fa.p, img, density,
-                                                     near_plane, out,
-                                                     blockIdx.x * kChaosBlock + threadIdx.x);
+  chaos_direct_point<real, DIM, FINAL, EQUAL, DEPTH, GENERAL>(
+      table, th, mt.n_maps, mt.n_search, mt.top_step, mt.flags, win, ra, fa.p, img, density,
+      near_plane, out, blockIdx.x * kChaosBlock + threadIdx.x);
 }
 
 template <typename real, int DIM, int FINAL, bool EQUAL, bool DEPTH>
@@ -34,8 +33,15 @@ static hipError_t launch_typed(const ChaosJob &j, hipStream_t s) {
   const MapTable<DIM> &mt = [&]() -> const MapTable<DIM> & {
     if constexpr (DIM == 2) return j.mt2; else return j.mt3;
   }();
-  hipLaunchKernelGGL((k_chaos<real, DIM, FINAL, EQUAL, DEPTH>), dim3(blocks), dim3(kChaosBlock),
-                     0, s, mt, j.win, j.ra, j.fa, j.img, j.density, j.near_plane, j.out);
+  // circle maps and reuse composition are 2D only
+  if (DIM == 2 && mt.flags != 0)
+    hipLaunchKernelGGL((k_chaos<real, DIM, FINAL, EQUAL, DEPTH, DIM == 2>), dim3(blocks),
+                       dim3(kChaosBlock), 0, s, mt, j.win, j.ra, j.fa, j.img, j.density,
+                       j.near_plane, j.out);
+  else
+    hipLaunchKernelGGL((k_chaos<real, DIM, FINAL, EQUAL, DEPTH, false>), dim3(blocks),
+                       dim3(kChaosBlock), 0, s, mt, j.win, j.ra, j.fa, j.img, j.density,
+                       j.near_plane, j.out);
   return hipGetLastError();
 }
 
