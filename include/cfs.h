@@ -204,6 +204,22 @@ int cfs_chaos_game(const cfs_system *sys, const cfs_run *run,
                    uint8_t *last_index, uint8_t *indices, void *workspace,
                    size_t workspace_bytes, void *stream);
 
+/* Measurement hook.  While enabled, every cfs_chaos_game call (up to 256
+ * calls between reads) records HIP events on its stream before its chaos
+ * kernel, after it, after the run-table transpose and after the tile
+ * accumulate (binned path; the last two phases are empty for the direct
+ * path), so a caller can time the chaos kernel alone on the stream it runs
+ * on.  Enabling costs four event records per launch slice and no device
+ * memory.  Default: off. */
+int cfs_timing_enable(int32_t enable);
+
+/* Waits for the recorded events and writes, for each recorded call i in
+ * call order (i < max_calls), the milliseconds of its phases summed over its
+ * launch slices: ms[3 i + 0] chaos kernel, ms[3 i + 1] transpose,
+ * ms[3 i + 2] accumulate (host float array of 3 * max_calls).  *n_calls gets
+ * the number of entries written; the record is then cleared. */
+int cfs_timing_read(float *ms, int32_t max_calls, int32_t *n_calls);
+
 /* Workspace in bytes that cfs_splat needs for this system, run and image. */
 size_t cfs_splat_workspace(const cfs_system *sys, const cfs_run *run,
                            const cfs_image *img, float sigma_px);

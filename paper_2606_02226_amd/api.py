@@ -152,6 +152,20 @@ def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
     return image
 
 
+def timing_enable(on=True):
+    """Record HIP events around the phases of every cfs_chaos_game call."""
+    check(_lib.load().cfs_timing_enable(1 if on else 0), "cfs_timing_enable")
+
+
+def timing_read(max_calls=256):
+    """[calls][3] milliseconds (chaos kernel, transpose, accumulate) of the
+    calls recorded since the last read."""
+    buf = (C.c_float * (3 * max_calls))()
+    n = C.c_int32(0)
+    check(_lib.load().cfs_timing_read(buf, max_calls, C.byref(n)), "cfs_timing_read")
+    return np.frombuffer(buf, np.float32, 3 * n.value).reshape(n.value, 3).copy()
+
+
 def chaos_workspace_bytes(system, run, image, precision="f32", splat_path="auto"):
     lib = _lib.load()
     sysc = system if isinstance(system, System) else System(system)

@@ -455,7 +455,11 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
   job.out.indices = indices;
   job.out.dropped = img->dropped;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!job.binned) return device_status(launch_chaos(job, s), "cfs_chaos_game");
+  const bool timed = timing_begin_call();
+  if (!job.binned) {
+    job.ev = timed ? timing_slice() : nullptr;
+    return device_status(launch_chaos(job, s), "cfs_chaos_game");
+  }
 
   // binned: slices of at most binned_slice() points share the workspace
   const uint32_t slice = binned_slice(run, job.depth);
@@ -471,6 +475,7 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const c
     if (last_index) sj.out.last_index = last_index + done;
     if (indices) sj.out.indices = indices + static_cast<size_t>(done) * run->n_iters;
     bind_workspace(&sj.ba, bp, workspace);
+    sj.ev = timed ? timing_slice() : nullptr;
     rc = device_status(launch_chaos_binned(sj, s), "cfs_chaos_game");
     if (rc) return rc;
   }

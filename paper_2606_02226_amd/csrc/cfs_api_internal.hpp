@@ -19,4 +19,11 @@ RunArgs make_run_args(const cfs_run *r);
 template <int DIM>
 int pack_table(const cfs_system *s, MapTable<DIM> *mt, bool *equal);
 
+// Measurement hook (cfs_timing_enable): timing_begin_call() opens the record
+// of one cfs_chaos_game call (false when timing is off or full); each launch
+// slice then asks timing_slice() for kPhaseEvents events to record (null when
+// not timing).
+bool timing_begin_call();
+const hipEvent_t *timing_slice();
+
 }  // namespace cfs

@@ -29,6 +29,7 @@ struct ChaosJob {
   float near_plane;
   Outputs out;
   BinArgs ba;
+  const hipEvent_t *ev;  // kPhaseEvents events to record around the phases, or null
 };
 
 // Records and table sizes of the binned splat for one launch of `points`.
@@ -40,9 +41,17 @@ struct BinPlan {
 BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems,
                  bool depth = false, uint32_t per_iter = 1);
 
+// Events recorded around the phases of one launch (chaos kernel, table
+// transpose, tile accumulate): before, between and after them.
+constexpr int kPhaseEvents = 4;
 hipError_t launch_chaos_binned(const ChaosJob &job, hipStream_t stream);
+// Record event i of a phase-event array on the stream (no-op for null).
+inline void mark_phase(const hipEvent_t *ev, int i, hipStream_t s) {
+  if (ev) (void)hipEventRecord(ev[i], s);
+}
 // Transpose the run table and add the binned count records into img.
-hipError_t launch_count_accumulate(const BinArgs &ba, uint32_t *img, hipStream_t stream);
+hipError_t launch_count_accumulate(const BinArgs &ba, uint32_t *img, hipStream_t stream,
+                                   const hipEvent_t *ev = nullptr);
 
 struct SceneJob {
   int precision;

@@ -103,12 +103,16 @@ BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t e
   return bp;
 }
 
-hipError_t launch_count_accumulate(const BinArgs &ba, uint32_t *img, hipStream_t s) {
+hipError_t launch_count_accumulate(const BinArgs &ba, uint32_t *img, hipStream_t s,
+                                   const hipEvent_t *ev) {
   hipError_t e = launch_transpose(ba.chunk_start, ba.tile_start, ba.n_chunks, ba.n_tiles + 1, s);
   if (e != hipSuccess) return e;
+  mark_phase(ev, 2, s);
   hipLaunchKernelGGL(k_tile_accumulate, dim3(ba.n_tiles), dim3(kAccBlock), 0, s, ba.records,
                      ba.tile_start, ba.n_chunks, ba.elems, img);
-  return hipGetLastError();
+  e = hipGetLastError();
+  mark_phase(ev, 3, s);
+  return e;
 }
 
 template <typename real, int DIM, int FINAL, bool EQUAL>
@@ -117,6 +121,7 @@ static hipError_t launch_binned_typed(const ChaosJob &j, hipStream_t s) {
     if constexpr (DIM == 2) return j.mt2; else return j.mt3;
   }();
   const uint32_t blocks = (j.ra.n_points + kBinBlock - 1) / kBinBlock;
+  mark_phase(j.ev, 0, s);
   // circle maps and reuse composition are 2D only
   if (DIM == 2 && mt.flags != 0)
     hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, DIM == 2>), dim3(blocks),
@@ -125,8 +130,14 @@ static hipError_t launch_binned_typed(const ChaosJob &j, hipStream_t s) {
     hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, false>), dim3(blocks),
                        dim3(kBinBlock), 0, s, mt, j.win, j.ra, j.fa, j.ba, j.out);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || j.ba.n_chunks == 0) return e;
-  return launch_count_accumulate(j.ba, static_cast<uint32_t *>(j.img), s);
+  mark_phase(j.ev, 1, s);
+  if (e != hipSuccess) return e;
+  if (j.ba.n_chunks == 0) {
+    mark_phase(j.ev, 2, s);
+    mark_phase(j.ev, 3, s);
+    return e;
+  }
+  return launch_count_accumulate(j.ba, static_cast<uint32_t *>(j.img), s, j.ev);
 }
 
 template <typename real, int DIM, int FINAL>
@@ -149,6 +160,7 @@ static hipError_t launch_binned_real(const ChaosJob &j, hipStream_t s) {
 template <typename real>
 static hipError_t launch_depth_binned(const ChaosJob &j, hipStream_t s) {
   const uint32_t blocks = (j.ra.n_points + kBinBlock - 1) / kBinBlock;
+  mark_phase(j.ev, 0, s);
   if (j.equal)
     hipLaunchKernelGGL((k_chaos_depth_binned<real, true>), dim3(blocks), dim3(kBinBlock), 0, s, j.mt3,
                        j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
@@ -156,17 +168,25 @@ static hipError_t launch_depth_binned(const ChaosJob &j, hipStream_t s) {
     hipLaunchKernelGGL((k_chaos_depth_binned<real, false>), dim3(blocks), dim3(kBinBlock), 0, s,
                        j.mt3, j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || j.ba.n_chunks == 0) return e;
-  e = launch_transpose(j.ba.chunk_start, j.ba.tile_start, j.ba.n_chunks, j.ba.n_tiles + 1, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_depth_accumulate, dim3(j.ba.n_tiles), dim3(kDAccBlock), 0, s, j.ba.drecords,
-                     j.ba.tile_start, j.ba.n_chunks, j.ba.elems,
-                     static_cast<unsigned long long *>(j.img), j.density);
-  return hipGetLastError();
+  mark_phase(j.ev, 1, s);
+  if (e == hipSuccess && j.ba.n_chunks != 0)
+    e = launch_transpose(j.ba.chunk_start, j.ba.tile_start, j.ba.n_chunks, j.ba.n_tiles + 1, s);
+  mark_phase(j.ev, 2, s);
+  if (e == hipSuccess && j.ba.n_chunks != 0) {
+    hipLaunchKernelGGL(k_depth_accumulate, dim3(j.ba.n_tiles), dim3(kDAccBlock), 0, s,
+                       j.ba.drecords, j.ba.tile_start, j.ba.n_chunks, j.ba.elems,
+                       static_cast<unsigned long long *>(j.img), j.density);
+    e = hipGetLastError();
+  }
+  mark_phase(j.ev, 3, s);
+  return e;
 }
 
 hipError_t launch_chaos_binned(const ChaosJob &job, hipStream_t stream) {
-  if (job.ra.n_points == 0) return hipSuccess;
+  if (job.ra.n_points == 0) {
+    for (int i = 0; i < kPhaseEvents; ++i) mark_phase(job.ev, i, stream);
+    return hipSuccess;
+  }
   if (job.depth)
     return job.precision == 1 ? launch_depth_binned<double>(job, stream)
                               : launch_depth_binned<float>(job, stream);

@@ -66,8 +66,13 @@ static hipError_t launch_real(const ChaosJob &j, hipStream_t s) {
 }
 
 hipError_t launch_chaos(const ChaosJob &job, hipStream_t stream) {
-  if (job.ra.n_points == 0) return hipSuccess;
-  return job.precision == 1 ? launch_real<double>(job, stream) : launch_real<float>(job, stream);
+  hipError_t e = hipSuccess;
+  mark_phase(job.ev, 0, stream);
+  if (job.ra.n_points != 0)
+    e = job.precision == 1 ? launch_real<double>(job, stream) : launch_real<float>(job, stream);
+  // the direct path has no transpose or accumulate phase
+  for (int i = 1; i < kPhaseEvents; ++i) mark_phase(job.ev, i, stream);
+  return e;
 }
 
 }  // namespace cfs

@@ -311,3 +311,29 @@ def test_l2_loss_validation(L):
     assert lib.cfs_l2_loss(None, None, 5, None, PLACEHOLDER, None, 0, None) == L.CFS_E_INVALID
     assert lib.cfs_l2_loss(PLACEHOLDER, PLACEHOLDER, 5, None, PLACEHOLDER, None, 0,
                            None) == L.CFS_E_WORKSPACE
+
+
+def test_batch_rejects_circle_maps(L):
+    lib = L.load()
+    out = C.c_void_p()
+    items = (L.CfsBatchItem * 1)()
+    s, keep = _system(L, n=3)
+    kinds = (C.c_int32 * 3)(0, 1, 0)
+    s.kind = kinds
+    items[0].sys = s
+    items[0].run = _run(L)
+    img = _image(L)
+    img.data = PLACEHOLDER
+    items[0].img = img
+    assert lib.cfs_batch_create(items, 1, None, C.byref(out)) == L.CFS_E_UNSUPPORTED
+    assert "affine maps only" in lib.cfs_last_error().decode()
+
+
+def test_timing_hook_without_calls(L):
+    lib = L.load()
+    n = C.c_int32(-1)
+    buf = (C.c_float * 6)()
+    assert lib.cfs_timing_enable(1) == L.CFS_OK
+    assert lib.cfs_timing_read(buf, 2, C.byref(n)) == L.CFS_OK and n.value == 0
+    assert lib.cfs_timing_enable(0) == L.CFS_OK
+    assert lib.cfs_timing_read(None, 0, None) == L.CFS_E_INVALID

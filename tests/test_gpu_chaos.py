@@ -478,3 +478,23 @@ def test_reuse_square_final_points(api, orc):
     print(f"reuse square f64: max |dp| {err.max():.2e}")
     assert np.mean(err > 1e-9) <= 1e-3
     assert rel_l1(got["image"], ref["image"]) <= 1e-4
+
+
+def test_timing_hook_phases(api):
+    # the measurement hook: one record per call, phases non-negative, the
+    # chaos kernel of the binned path takes time, the direct path has no
+    # transpose or accumulate phase
+    w = W.sierpinski(n_points=1 << 16)
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.timing_read()
+    api.timing_enable(True)
+    try:
+        api.chaos_game(w["system"], w["run"], img, precision="f32", splat_path="binned")
+        api.chaos_game(w["system"], w["run"], img, precision="f32", splat_path="direct")
+    finally:
+        api.timing_enable(False)
+    ph = api.timing_read()
+    assert ph.shape == (2, 3)
+    assert np.all(ph >= 0) and ph[0, 0] > 0 and ph[1, 0] > 0
+    assert ph[1, 1] < 0.05 and ph[1, 2] < 0.05
+    assert api.timing_read().shape == (0, 3)
