@@ -69,6 +69,51 @@ def measured_traffic(precision):
     return t.get("bytes_per_launch")
 
 
+def _pmc_rows(directory, counter):
+    """(kernel name, value) of every dispatch in a rocprofv3 --pmc CSV run."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {directory}")
+    return rows
+
+
+def summarise_pmc(fetch_dir, write_dir, precision):
+    """Write profiles/traffic_cfs_square_<precision>.json from two rocprofv3
+    --pmc runs of this benchmark with --calibration-copy (FETCH_SIZE, then
+    WRITE_SIZE; both in KiB per dispatch).  Each counter is scaled by the
+    factor that makes the 256 MiB calibration copy read and write 256 MiB."""
+    copy_bytes = 256 << 20
+    out = {"source_digest": source_digest(), "precision": precision,
+           "unit": "bytes per launch", "calibration": {}, "kernels": {}}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _pmc_rows(d, counter)
+        copies = [v for k, v in rows if "copyBuffer" in k or "copy" in k.lower()]
+        scale = copy_bytes / (max(copies) * 1024.0)
+        out["calibration"][counter] = {"copy_kib": max(copies), "scale": scale}
+        for name, key in (("k_chaos_binned", "chaos_kernel"), ("k_transpose", "table_transpose"),
+                          ("k_tile_accumulate", "tile_accumulate")):
+            vals = [v for k, v in rows if name in k]
+            if vals:
+                out["kernels"].setdefault(key, {})[counter] = \
+                    float(np.mean(vals)) * 1024.0 * scale
+    ck = out["kernels"].get("chaos_kernel", {})
+    out["bytes_per_launch"] = ck.get("FETCH_SIZE", 0.0) + ck.get("WRITE_SIZE", 0.0)
+    out["command"] = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -d DIR "
+                      "-- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-forms "
+                      f"--calibration-copy --precision {precision}")
+    path = os.path.join(ROOT, "profiles", f"traffic_cfs_square_{precision}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(w, n_sample):
     import oracle
     oracle.build(force=False)
@@ -201,7 +246,13 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="copy 256 MiB once before timing (for counter calibration)")
+    ap.add_argument("--summarise-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_cfs_square_<precision>.json from two "
+                         "rocprofv3 --pmc output folders and exit (no GPU needed)")
     args = ap.parse_args()
+    if args.summarise_pmc:
+        summarise_pmc(*args.summarise_pmc, args.precision)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
                                    "multi-GPU runs are not part of this build"}))

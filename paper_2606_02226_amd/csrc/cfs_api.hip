@@ -298,6 +298,8 @@ void bind_workspace(BinArgs *ba, const BinPlan &bp, void *workspace) {
   ba->flushes = bp.flushes;
   ba->n_tiles = bp.n_tiles;
   ba->elems = bp.elems;
+  ba->parts = bp.parts;
+  ba->log2g = bp.log2g;
 }
 
 // Scene objects: validation and packing into kernel arguments.

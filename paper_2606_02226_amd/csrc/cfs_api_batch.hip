@@ -154,8 +154,14 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
     for (uint32_t blk = 0; blk < bp.blocks; blk += p.blocks_per_item)
       emit.push_back(EmitItem{static_cast<uint32_t>(i), blk,
                               std::min<uint32_t>(p.blocks_per_item, bp.blocks - blk)});
+    d.log2g = bp.log2g;
     if (d.n_chunks) {
-      for (uint32_t t = 0; t < d.n_tiles; ++t) acc.push_back(AccItem{static_cast<uint32_t>(i), t});
+      const uint32_t parts = bp.parts;
+      for (uint32_t t = 0; t < d.n_tiles; ++t)
+        for (uint32_t q = 0; q < parts; ++q)
+          acc.push_back(AccItem{static_cast<uint32_t>(i), t,
+                                static_cast<uint32_t>(static_cast<uint64_t>(d.n_chunks) * q / parts),
+                                static_cast<uint32_t>(static_cast<uint64_t>(d.n_chunks) * (q + 1) / parts)});
       for (uint32_t by = 0; by < (d.n_chunks + 63) / 64; ++by)
         for (uint32_t bx = 0; bx < (d.n_tiles + 1 + 63) / 64; ++bx)
           trans.push_back(TransItem{static_cast<uint32_t>(i), bx, by});
@@ -170,6 +176,12 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
   });
   uint32_t n32 = 0;
   for (const EmitItem &it : emit) n32 += desc[it.inst].precision == 0 ? 1u : 0u;
+  // accumulate items by expected record count, largest first
+  std::stable_sort(acc.begin(), acc.end(), [&](const AccItem &a, const AccItem &b2) {
+    const double wa = static_cast<double>(a.c_hi - a.c_lo) / desc[a.inst].n_tiles;
+    const double wb = static_cast<double>(b2.c_hi - b2.c_lo) / desc[b2.inst].n_tiles;
+    return wa > wb;
+  });
 
   cfs_batch *b = new cfs_batch();
   b->device = dev;

@@ -22,6 +22,7 @@ struct InstDesc {
   uint64_t table_base;  // first word of the instance's run-start tables
   int32_t equal;
   int32_t precision;    // 0 = FP32 positions, 1 = FP64
+  uint32_t log2g;       // accumulate lanes per run: 2^log2g
 };
 
 struct EmitItem {
@@ -29,7 +30,7 @@ struct EmitItem {
 };
 
 struct AccItem {
-  uint32_t inst, tile;
+  uint32_t inst, tile, c_lo, c_hi;  // chunk range [c_lo, c_hi) of the tile
 };
 
 struct TransItem {

@@ -330,48 +330,54 @@ __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
   __syncthreads();
 }
 
-// Image tile t of one run: LDS histogram of the tile's records from every
-// chunk, then added into the image (the workgroup owns the tile).  Each lane
-// walks the run of one chunk with 8-byte loads (4 records), four loads in
-// flight; runs start anywhere, so loads start at the 4-record boundary below
-// the run and records outside [start, end) are skipped.  Every thread of the
-// workgroup calls it; `tile` is kTileElems words of LDS.
+// Part [c_lo, c_hi) of the chunks of image tile t: an LDS histogram of the
+// tile's records in those chunks, added into the image -- with a plain
+// read-modify-write when the part is every chunk (the workgroup then owns
+// the tile), with device atomics when several parts share the tile.  Runs
+// are walked by groups of 2^log2g lanes (one run per group, 4 records per
+// lane per 8-byte load from the 4-record boundary below the run start;
+// records outside [start, end) are skipped): the host picks the group size
+// from the mean run length, so short runs keep many runs in flight and long
+// runs are read with coalesced loads.  Every thread of the workgroup calls
+// it; `tile` is kTileElems words of LDS.
+__device__ inline void count_records(uint32_t *tile, uint2 v, uint32_t at, uint32_t s,
+                                     uint32_t e) {
+  const uint32_t r4[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const uint32_t idx = at + m;
+    if (idx >= s && idx < e) atomicAdd(&tile[r4[m]], 1u);
+  }
+}
+
 __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
                                        const uint32_t *__restrict__ tile_start, uint32_t n_chunks,
-                                       uint32_t elems, uint32_t *__restrict__ img, uint32_t t,
+                                       uint32_t c_lo, uint32_t c_hi, uint32_t elems,
+                                       uint32_t *__restrict__ img, uint32_t t, uint32_t log2g,
                                        uint32_t *tile) {
-  const int tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < kTileElems; i += kAccBlock) tile[i] = 0u;
   __syncthreads();
   const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
   const uint32_t *row1 = row0 + n_chunks;
-  for (uint32_t c = tid; c < n_chunks; c += kAccBlock) {
-    const uint32_t s = row0[c];
-    const uint32_t e = row1[c];
-    for (uint32_t i = s & ~3u; i < e; i += 16u) {
-      uint2 v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const uint32_t at = i + 4u * u;
-        v[u] = at < e ? *reinterpret_cast<const uint2 *>(rec + at) : make_uint2(0u, 0u);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const uint32_t r4[4] = {v[u].x & 0xFFFFu, v[u].x >> 16, v[u].y & 0xFFFFu, v[u].y >> 16};
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const uint32_t idx = i + 4u * u + m;
-          if (idx >= s && idx < e) atomicAdd(&tile[r4[m]], 1u);
-        }
-      }
-    }
+  const uint32_t g = 1u << log2g, lane = tid & (g - 1u);
+  const uint32_t groups = kAccBlock >> log2g;
+  for (uint32_t c = c_lo + (tid >> log2g); c < c_hi; c += groups) {
+    const uint32_t s = row0[c], e = row1[c];
+    for (uint32_t i = (s & ~3u) + 4u * lane; i < e; i += 4u * g)
+      count_records(tile, *reinterpret_cast<const uint2 *>(rec + i), i, s, e);
   }
   __syncthreads();
   const uint32_t base = t * kTileElems;
   const uint32_t len = min(kTileElems, elems - base);
+  const bool whole = c_lo == 0 && c_hi == n_chunks;
   for (uint32_t i = tid; i < len; i += kAccBlock) {
     const uint32_t v = tile[i];
-    if (v) img[base + i] += v;
+    if (!v) continue;
+    if (whole)
+      img[base + i] += v;
+    else
+      __hip_atomic_fetch_add(img + base + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
 }

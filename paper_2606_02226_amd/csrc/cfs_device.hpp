@@ -137,14 +137,15 @@ __device__ __forceinline__ void apply_map(const real *__restrict__ table, int k,
       circle_map<real>(r[4], p);
       return;
     }
+    // two fused multiply-adds per coordinate
     const real x = p[0], y = p[1];
-    p[0] = r[0] * x + r[1] * y + r[4];
-    p[1] = r[2] * x + r[3] * y + r[5];
+    p[0] = fma(r[0], x, fma(r[1], y, r[4]));
+    p[1] = fma(r[2], x, fma(r[3], y, r[5]));
   } else {
     const real x = p[0], y = p[1], z = p[2];
-    p[0] = r[0] * x + r[1] * y + r[2] * z + r[9];
-    p[1] = r[3] * x + r[4] * y + r[5] * z + r[10];
-    p[2] = r[6] * x + r[7] * y + r[8] * z + r[11];
+    p[0] = fma(r[0], x, fma(r[1], y, fma(r[2], z, r[9])));
+    p[1] = fma(r[3], x, fma(r[4], y, fma(r[5], z, r[10])));
+    p[2] = fma(r[6], x, fma(r[7], y, fma(r[8], z, r[11])));
   }
 }
 
@@ -173,10 +174,68 @@ __device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
 // ---------------------------------------------------------------------------
 // Composed transforms on the copy q of p (p is never modified).
 // ---------------------------------------------------------------------------
+// FP64 sine and cosine for the transforms.  Arguments with |a| < 2^19 pi/2
+// are reduced by pi/2 after Cody and Waite (Software Manual for the
+// Elementary Functions, 1980): k = rint(2a/pi), r = a - k P1 - k P2 - k P3
+// with pi/2 = P1 + P2 + P3, P1 and P2 of 33 significant bits (so k P1, k P2
+// are exact for |k| <= 2^19).  sin r and cos r on [-pi/4, pi/4] are their
+// Taylor series to degree 15 and 16 (truncation below 5e-17), and the
+// quadrant k mod 4 swaps and negates them.  Other arguments (large, infinite
+// or NaN) take the library's sincos; no lane of the workloads here does.
+__device__ __forceinline__ void sincos_f64(double a, double *sn, double *cs) {
+  if (!(fabs(a) < 823549.0)) {
+    sincos(a, sn, cs);
+    return;
+  }
+  const double k = rint(a * 0.63661977236758134308);
+  double r = fma(-k, 0x1.921fb54400000p+0, a);
+  r = fma(-k, 0x1.0b4611a600000p-34, r);
+  r = fma(-k, 0x1.3198a2e037073p-69, r);
+  const double x2 = r * r;
+  double ps = -1.0 / 1307674368000.0;
+  ps = fma(ps, x2, 1.0 / 6227020800.0);
+  ps = fma(ps, x2, -1.0 / 39916800.0);
+  ps = fma(ps, x2, 1.0 / 362880.0);
+  ps = fma(ps, x2, -1.0 / 5040.0);
+  ps = fma(ps, x2, 1.0 / 120.0);
+  ps = fma(ps, x2, -1.0 / 6.0);
+  const double sr = fma(r * x2, ps, r);
+  double pc = 1.0 / 20922789888000.0;
+  pc = fma(pc, x2, -1.0 / 87178291200.0);
+  pc = fma(pc, x2, 1.0 / 479001600.0);
+  pc = fma(pc, x2, -1.0 / 3628800.0);
+  pc = fma(pc, x2, 1.0 / 40320.0);
+  pc = fma(pc, x2, -1.0 / 720.0);
+  pc = fma(pc, x2, 1.0 / 24.0);
+  pc = fma(pc, x2, -0.5);
+  const double cr = fma(pc, x2, 1.0);
+  const int q = static_cast<int>(k);
+  const double s0 = (q & 1) ? cr : sr;
+  const double c0 = (q & 1) ? sr : cr;
+  *sn = (q & 2) ? -s0 : s0;
+  *cs = ((q + 1) & 2) ? -c0 : c0;
+}
+
+// FP64 square root for the transforms (a radius that feeds an angle or a
+// scale): the hardware reciprocal square root estimate, one coupled Newton
+// step on (sqrt a, 1 / (2 sqrt a)) and a final residual correction, which
+// lands within an ulp or two; a <= 1e-300 gives 0.
+__device__ __forceinline__ double sqrt_f64(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y;
+  double h = 0.5 * y;
+  const double e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  const double d = fma(-g, g, a);
+  g = fma(d, h, g);
+  return a > 1e-300 ? g : 0.0;
+}
+
 __device__ __forceinline__ void sincos_r(float a, float *s, float *c) { sincosf(a, s, c); }
-__device__ __forceinline__ void sincos_r(double a, double *s, double *c) { sincos(a, s, c); }
+__device__ __forceinline__ void sincos_r(double a, double *s, double *c) { sincos_f64(a, s, c); }
 __device__ __forceinline__ float sqrt_r(float a) { return sqrtf(a); }
-__device__ __forceinline__ double sqrt_r(double a) { return sqrt(a); }
+__device__ __forceinline__ double sqrt_r(double a) { return sqrt_f64(a); }
 __device__ __forceinline__ float cos_r(float a) { return cosf(a); }
 __device__ __forceinline__ double cos_r(double a) { return cos(a); }
 

@@ -34,9 +34,13 @@ struct ChaosJob {
 
 // Records and table sizes of the binned splat for one launch of `points`.
 struct BinPlan {
-  uint32_t blocks, flushes, n_chunks, n_tiles, elems;
+  uint32_t blocks, flushes, n_chunks, n_tiles, elems, parts, log2g;
   size_t records_bytes, table_bytes;
 };
+// Accumulate launch shape for `records` count records in n_chunks chunks over
+// n_tiles tiles: workgroups per tile and lanes per run (2^log2g).
+void acc_shape(uint64_t records, uint32_t n_chunks, uint32_t n_tiles, uint32_t *parts,
+               uint32_t *log2g);
 // per_iter: records a lane stages per step after burn-in (objects of a scene).
 BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems,
                  bool depth = false, uint32_t per_iter = 1);

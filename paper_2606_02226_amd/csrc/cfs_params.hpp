@@ -72,6 +72,9 @@ constexpr int kDTileBits = 13;
 constexpr uint32_t kDTileElems = 1u << kDTileBits;
 constexpr int kDAccBlock = 512;
 
+// The count accumulate aims at this many workgroups (two per CU of MI355X).
+constexpr uint32_t kAccTargetGroups = 512;
+
 struct BinArgs {
   uint16_t *records;     // [n_chunks][kChunkCap] in-tile offsets, runs by tile
   uint2 *drecords;       // depth images: [n_chunks][kDCap] (offset | index << 13, depth)
@@ -81,6 +84,8 @@ struct BinArgs {
   uint32_t flushes;      // chunks per workgroup
   uint32_t n_tiles;
   uint32_t elems;        // image elements (channels * height * width)
+  uint32_t parts;        // accumulate workgroups per tile (chunk ranges)
+  uint32_t log2g;        // accumulate lanes per run: 2^log2g
 };
 
 // Gaussian splat: 512-lane workgroups collect kGSlots splats per lane as

@@ -75,8 +75,8 @@ __global__ __launch_bounds__(kAccBlock) void k_batch_accumulate(const InstDesc *
     if (it >= n_items) break;
     const AccItem item = items[it];
     const InstDesc &d = desc[item.inst];
-    tile_accumulate(records + d.rec_base, tables + d.table_base, d.n_chunks, d.elems, d.img,
-                    item.tile, tile);
+    tile_accumulate(records + d.rec_base, tables + d.table_base, d.n_chunks, item.c_lo, item.c_hi,
+                    d.elems, d.img, item.tile, d.log2g, tile);
   }
 }
 

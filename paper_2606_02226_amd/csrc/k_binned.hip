@@ -64,13 +64,19 @@ __global__ __launch_bounds__(kDAccBlock) void k_depth_accumulate(const uint2 *__
                         xcd_item(blockIdx.x, gridDim.x), keys, counts);
 }
 
-// One workgroup per image tile.
+// One workgroup per (image tile, chunk range); the parts of a tile are
+// neighbours in the XCD-contiguous order.
 __global__ __launch_bounds__(kAccBlock) void k_tile_accumulate(const uint16_t *__restrict__ rec,
                                                                const uint32_t *__restrict__ tile_start,
                                                                uint32_t n_chunks, uint32_t elems,
-                                                               uint32_t *__restrict__ img) {
+                                                               uint32_t *__restrict__ img,
+                                                               uint32_t parts, uint32_t log2g) {
   __shared__ uint32_t tile[kTileElems];
-  tile_accumulate(rec, tile_start, n_chunks, elems, img, xcd_item(blockIdx.x, gridDim.x), tile);
+  const uint32_t item = xcd_item(blockIdx.x, gridDim.x);
+  const uint32_t t = item / parts, part = item % parts;
+  const uint32_t c_lo = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * part / parts);
+  const uint32_t c_hi = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * (part + 1) / parts);
+  tile_accumulate(rec, tile_start, n_chunks, c_lo, c_hi, elems, img, t, log2g, tile);
 }
 
 __global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ in,
@@ -88,6 +94,21 @@ hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, ui
   return hipGetLastError();
 }
 
+void acc_shape(uint64_t records, uint32_t n_chunks, uint32_t n_tiles, uint32_t *parts,
+               uint32_t *log2g) {
+  // mean run length -> lanes per run (a lane loads 4 records)
+  const uint64_t runs = static_cast<uint64_t>(n_chunks) * (n_tiles ? n_tiles : 1);
+  const uint64_t mean = runs ? records / runs : 0;
+  uint32_t lg = 0;
+  while (lg < 6 && (4ull << lg) < mean) ++lg;
+  *log2g = lg;
+  // enough workgroups for two per CU, but at least one pass of groups each
+  const uint32_t groups = kAccBlock >> lg;
+  uint32_t p = n_tiles ? (kAccTargetGroups + n_tiles - 1) / n_tiles : 1;
+  const uint32_t pmax = n_chunks / groups > 1 ? n_chunks / groups : 1;
+  *parts = p < 1 ? 1 : (p > pmax ? pmax : p);
+}
+
 BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems, bool depth,
                  uint32_t per_iter) {
   BinPlan bp{};
@@ -97,6 +118,8 @@ BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t e
   bp.n_chunks = bp.blocks * bp.flushes;
   bp.n_tiles = depth ? (elems + kDTileElems - 1) / kDTileElems : (elems + kTileElems - 1) / kTileElems;
   bp.elems = elems;
+  acc_shape(static_cast<uint64_t>(points) * (n_iters - burn_in) * per_iter, bp.n_chunks, bp.n_tiles,
+            &bp.parts, &bp.log2g);
   bp.records_bytes = depth ? static_cast<size_t>(bp.n_chunks) * kDCap * sizeof(uint2)
                            : static_cast<size_t>(bp.n_chunks) * kChunkCap * sizeof(uint16_t);
   bp.table_bytes = static_cast<size_t>(bp.n_tiles + 1) * bp.n_chunks * sizeof(uint32_t);  // each of two
@@ -108,8 +131,8 @@ hipError_t launch_count_accumulate(const BinArgs &ba, uint32_t *img, hipStream_t
   hipError_t e = launch_transpose(ba.chunk_start, ba.tile_start, ba.n_chunks, ba.n_tiles + 1, s);
   if (e != hipSuccess) return e;
   mark_phase(ev, 2, s);
-  hipLaunchKernelGGL(k_tile_accumulate, dim3(ba.n_tiles), dim3(kAccBlock), 0, s, ba.records,
-                     ba.tile_start, ba.n_chunks, ba.elems, img);
+  hipLaunchKernelGGL(k_tile_accumulate, dim3(ba.n_tiles * ba.parts), dim3(kAccBlock), 0, s,
+                     ba.records, ba.tile_start, ba.n_chunks, ba.elems, img, ba.parts, ba.log2g);
   e = hipGetLastError();
   mark_phase(ev, 3, s);
   return e;

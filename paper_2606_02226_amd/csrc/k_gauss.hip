@@ -195,51 +195,61 @@ __device__ __forceinline__ void tap_weights(float x, int i0, int lo, int hi, con
   }
 }
 
+// One workgroup per (tile, chunk range): the records of its own tile only
+// (binned by their first tap, so every footprint starts inside the tile and
+// ends at most TAPS - 1 pixels past its right and lower edges) are read once,
+// their taps summed into an LDS tile with that halo, and the tile plus halo
+// is added into the density with device atomics (neighbouring tiles and the
+// other chunk ranges of the tile add into the same pixels; the FP32 sums
+// have no fixed order).  Runs are walked by groups of 2^log2g lanes, one
+// record per lane.
 template <int TAPS>
 __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *__restrict__ rec,
                                                                  const uint32_t *__restrict__ tile_start,
                                                                  uint32_t n_chunks, GaussParams gp,
+                                                                 uint32_t parts, uint32_t log2g,
                                                                  float *__restrict__ dens) {
-  __shared__ float acc[kGTile * kGTile];
-  const int tid = threadIdx.x;
-  const uint32_t t = xcd_item(blockIdx.x, gridDim.x);
+  constexpr int H = kGTile + TAPS - 1;  // tile plus halo, per axis
+  __shared__ float acc[H * H];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t item = xcd_item(blockIdx.x, gridDim.x);
+  const uint32_t t = item / parts, part = item % parts;
+  const uint32_t c_lo = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * part / parts);
+  const uint32_t c_hi = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * (part + 1) / parts);
   const int tx = t % gp.tiles_x, ty = t / gp.tiles_x;
   const int x0 = tx * kGTile, y0 = ty * kGTile;
-  const int xlo = x0, xhi = min(x0 + kGTile, gp.width);
-  const int ylo = y0, yhi = min(y0 + kGTile, gp.height);
-  for (int i = tid; i < kGTile * kGTile; i += kGAccBlock) acc[i] = 0.0f;
+  const int xhi = min(x0 + H, gp.width), yhi = min(y0 + H, gp.height);
+  for (uint32_t i = tid; i < H * H; i += kGAccBlock) acc[i] = 0.0f;
   __syncthreads();
-  // each lane walks the runs of its chunks in the tile and its left, upper
-  // and upper-left neighbours
-  for (uint32_t c = tid; c < n_chunks; c += kGAccBlock) {
-    for (int src = 0; src < 4; ++src) {
-      const int sx = tx - (src & 1), sy = ty - (src >> 1);
-      if (sx < 0 || sy < 0) continue;
-      const uint32_t *row0 = tile_start + static_cast<size_t>(sy * gp.tiles_x + sx) * n_chunks;
-      const uint32_t s = row0[c], e = row0[n_chunks + c];
-      for (uint32_t i = s; i < e; ++i) {
-        const float2 r = rec[i];
-        const int i0 = first_tap(r.x, gp.R), j0 = first_tap(r.y, gp.R);
-        if (i0 >= xhi || i0 + TAPS <= xlo || j0 >= yhi || j0 + TAPS <= ylo) continue;
-        float gx[TAPS], gy[TAPS];
-        tap_weights<TAPS>(r.x, i0, xlo, xhi, gp, gx);
-        tap_weights<TAPS>(r.y, j0, ylo, yhi, gp, gy);
+  const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
+  const uint32_t *row1 = row0 + n_chunks;
+  const uint32_t g = 1u << log2g, lane = tid & (g - 1u), groups = kGAccBlock >> log2g;
+  for (uint32_t c = c_lo + (tid >> log2g); c < c_hi; c += groups) {
+    const uint32_t s = row0[c], e = row1[c];
+    for (uint32_t i = s + lane; i < e; i += g) {
+      const float2 r = rec[i];
+      const int i0 = first_tap(r.x, gp.R), j0 = first_tap(r.y, gp.R);
+      // taps left of or above the tile are off the image (first taps are
+      // clamped to 0 for binning), so lo = x0, y0 drops exactly those
+      float gx[TAPS], gy[TAPS];
+      tap_weights<TAPS>(r.x, i0, x0, xhi, gp, gx);
+      tap_weights<TAPS>(r.y, j0, y0, yhi, gp, gy);
 #pragma unroll
-        for (int b = 0; b < TAPS; ++b) {
-          if (gy[b] == 0.0f) continue;
-          const float wy = gy[b] * gp.weight;
+      for (int b = 0; b < TAPS; ++b) {
+        if (gy[b] == 0.0f) continue;
+        const float wy = gy[b] * gp.weight;
 #pragma unroll
-          for (int a = 0; a < TAPS; ++a)
-            if (gx[a] != 0.0f) atomicAdd(&acc[(j0 + b - y0) * kGTile + (i0 + a - x0)], gx[a] * wy);
-        }
+        for (int a = 0; a < TAPS; ++a)
+          if (gx[a] != 0.0f) atomicAdd(&acc[(j0 + b - y0) * H + (i0 + a - x0)], gx[a] * wy);
       }
     }
   }
   __syncthreads();
-  for (int i = tid; i < kGTile * kGTile; i += kGAccBlock) {
-    const int px = x0 + (i & (kGTile - 1)), py = y0 + (i >> kGTileLog);
+  for (uint32_t i = tid; i < H * H; i += kGAccBlock) {
+    const int px = x0 + static_cast<int>(i % H), py = y0 + static_cast<int>(i / H);
     const float v = acc[i];
-    if (px < gp.width && py < gp.height && v != 0.0f) dens[static_cast<size_t>(py) * gp.width + px] += v;
+    if (px < gp.width && py < gp.height && v != 0.0f)
+      atomicAdd(dens + static_cast<size_t>(py) * gp.width + px, v);
   }
 }
 
@@ -436,12 +446,24 @@ hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
   if (e != hipSuccess) return e;
   e = launch_transpose(j.gb.chunk_start, j.gb.tile_start, j.gb.n_chunks, j.gb.n_tiles + 1, s);
   if (e != hipSuccess) return e;
+  // lanes per run from the mean run length (one record per lane), and enough
+  // workgroups per tile for eight small workgroups per CU while each keeps
+  // one pass of groups
+  const uint64_t runs = static_cast<uint64_t>(j.gb.n_chunks) * j.gb.n_tiles;
+  const uint64_t mean = runs ? static_cast<uint64_t>(j.ra.n_points) * (j.ra.n_iters - j.ra.burn_in) / runs : 0;
+  uint32_t lg = 0;
+  while (lg < 6 && (1ull << lg) < mean) ++lg;
+  const uint32_t groups = kGAccBlock >> lg;
+  uint32_t parts = (4 * kAccTargetGroups + j.gb.n_tiles - 1) / j.gb.n_tiles;
+  const uint32_t pmax = j.gb.n_chunks / groups > 1 ? j.gb.n_chunks / groups : 1;
+  if (parts > pmax) parts = pmax;
+  if (parts < 1) parts = 1;
   if (j.gp.taps <= 6)
-    hipLaunchKernelGGL(k_splat_accumulate<6>, dim3(j.gb.n_tiles), dim3(kGAccBlock), 0, s,
-                       j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, j.dens);
+    hipLaunchKernelGGL(k_splat_accumulate<6>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
+                       j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, parts, lg, j.dens);
   else
-    hipLaunchKernelGGL(k_splat_accumulate<16>, dim3(j.gb.n_tiles), dim3(kGAccBlock), 0, s,
-                       j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, j.dens);
+    hipLaunchKernelGGL(k_splat_accumulate<16>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
+                       j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, parts, lg, j.dens);
   return hipGetLastError();
 }
 
