@@ -276,8 +276,10 @@ int cfs_chaos_scene(const cfs_system *sys, const cfs_object *objects, int32_t n_
  * (s = sigma_px; d = pixel centre - point, in pixels; pixel (i, j) gets
  * g(i + 0.5 - x) g(j + 0.5 - y); taps off the image are skipped) into the
  * FP32 density img (kind CFS_IMAGE_F32_DENSITY, one channel), which
- * ACCUMULATES sum(w) / (N (T - B)).  The order of FP32 additions is not
- * fixed, so results agree with any other order up to rounding.
+ * ACCUMULATES sum(w) / (N (T - B)).  Each tap weight is rounded to a
+ * multiple of 2^-31 and summed exactly per image tile; the tiles' sums are
+ * added in FP32 in no fixed order, so results agree with any other order up
+ * to rounding.
  *   ckpt: device, nullable; float [ceil(n_iters / ckpt_every)][n_points][2]:
  *     positions at iterations 0, c, 2c, ... (c = ckpt_every in 1..16), from
  *     which cfs_splat_backward recomputes its segments.
@@ -297,8 +299,9 @@ size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run);
  *   dL/dA_{k_t} += lam_t p_{t-1}^T, dL/db_{k_t} += lam_t
  * (s_t = dL/dp_t through the splat of step t; zero for t <= B).
  * grad (device float [n_maps][6] = a00 a01 a10 a11 b0 b1) is OVERWRITTEN;
- * the reduction is deterministic (per-lane sums, then a fixed-order tree and a
- * fixed-order sum over workgroups; no floating-point atomics).  ckpt must be
+ * the reduction is deterministic (per-lane sums, a fixed-order tree per
+ * workgroup, and a fixed-order two-level FP64 sum over workgroups; no
+ * floating-point atomics).  ckpt must be
  * the forward's checkpoints for the same system, run and ckpt_every (1..16).
  * Systems of at most 8 maps. */
 int cfs_splat_backward(const cfs_system *sys, const cfs_run *run,

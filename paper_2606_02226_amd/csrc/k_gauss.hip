@@ -197,12 +197,15 @@ __device__ __forceinline__ void tap_weights(float x, int i0, int lo, int hi, con
 
 // One workgroup per (tile, chunk range): the records of its own tile only
 // (binned by their first tap, so every footprint starts inside the tile and
-// ends at most TAPS - 1 pixels past its right and lower edges) are read once,
-// their taps summed into an LDS tile with that halo, and the tile plus halo
-// is added into the density with device atomics (neighbouring tiles and the
-// other chunk ranges of the tile add into the same pixels; the FP32 sums
-// have no fixed order).  Runs are walked by groups of 2^log2g lanes, one
-// record per lane.
+// ends at most TAPS - 1 pixels past its right and lower edges) are read once
+// and their taps summed into an LDS tile with that halo.  The LDS sums are
+// integers: each tap adds round(g(dx) g(dy) 2^31) to a 64-bit counter (LDS
+// integer atomics run far faster than floating-point ones, and integer sums
+// do not depend on their order), so a pixel holds its tap sum to 2^-31 per
+// tap.  The tile plus halo is then scaled by 2^-31 / (N (T - B)) and added
+// into the density with device float atomics (neighbouring tiles and the
+// other chunk ranges of the tile add into the same pixels).  Runs are walked
+// by groups of 2^log2g lanes, one record per lane.
 template <int TAPS>
 __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *__restrict__ rec,
                                                                  const uint32_t *__restrict__ tile_start,
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
                                                                  uint32_t parts, uint32_t log2g,
                                                                  float *__restrict__ dens) {
   constexpr int H = kGTile + TAPS - 1;  // tile plus halo, per axis
-  __shared__ float acc[H * H];
+  __shared__ unsigned long long acc[H * H];
   const uint32_t tid = threadIdx.x;
   const uint32_t item = xcd_item(blockIdx.x, gridDim.x);
   const uint32_t t = item / parts, part = item % parts;
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
   const int tx = t % gp.tiles_x, ty = t / gp.tiles_x;
   const int x0 = tx * kGTile, y0 = ty * kGTile;
   const int xhi = min(x0 + H, gp.width), yhi = min(y0 + H, gp.height);
-  for (uint32_t i = tid; i < H * H; i += kGAccBlock) acc[i] = 0.0f;
+  for (uint32_t i = tid; i < H * H; i += kGAccBlock) acc[i] = 0ull;
   __syncthreads();
   const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
   const uint32_t *row1 = row0 + n_chunks;
@@ -237,19 +240,23 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
 #pragma unroll
       for (int b = 0; b < TAPS; ++b) {
         if (gy[b] == 0.0f) continue;
-        const float wy = gy[b] * gp.weight;
+        const float wy = gy[b] * 2147483648.0f;  // 2^31; g <= 1 per axis
 #pragma unroll
         for (int a = 0; a < TAPS; ++a)
-          if (gx[a] != 0.0f) atomicAdd(&acc[(j0 + b - y0) * H + (i0 + a - x0)], gx[a] * wy);
+          if (gx[a] != 0.0f)
+            atomicAdd(&acc[(j0 + b - y0) * H + (i0 + a - x0)],
+                      static_cast<unsigned long long>(__float2uint_rn(gx[a] * wy)));
       }
     }
   }
   __syncthreads();
+  const double unit = static_cast<double>(gp.weight) * 0x1p-31;
   for (uint32_t i = tid; i < H * H; i += kGAccBlock) {
     const int px = x0 + static_cast<int>(i % H), py = y0 + static_cast<int>(i / H);
-    const float v = acc[i];
-    if (px < gp.width && py < gp.height && v != 0.0f)
-      atomicAdd(dens + static_cast<size_t>(py) * gp.width + px, v);
+    const unsigned long long v = acc[i];
+    if (px < gp.width && py < gp.height && v != 0ull)
+      atomicAdd(dens + static_cast<size_t>(py) * gp.width + px,
+                static_cast<float>(static_cast<double>(v) * unit));
   }
 }
 
@@ -408,13 +415,25 @@ __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, R
   }
 }
 
-// grad[i] = sum over workgroups b in order of partials[b][i] (FP64 sum).
-__global__ void k_grad_reduce(const float *partials, uint32_t blocks, int ng6, int n6, float *grad) {
-  const int i = threadIdx.x;
-  if (i >= n6) return;
+// grad[i] = the FP64 sum over workgroups b of partials[b][i], one workgroup
+// per entry i: thread j sums the workgroups b = j (mod 256) in order, then a
+// fixed tree adds the 256 sums, so the result depends only on the inputs.
+constexpr int kReduceBlock = 256;
+
+__global__ __launch_bounds__(kReduceBlock) void k_grad_reduce(const float *partials, uint32_t blocks,
+                                                              int ng6, float *grad) {
+  __shared__ double lds[kReduceBlock];
+  const int i = blockIdx.x, tid = threadIdx.x;
   double s = 0.0;
-  for (uint32_t b = 0; b < blocks; ++b) s += static_cast<double>(partials[static_cast<size_t>(b) * ng6 + i]);
-  grad[i] = static_cast<float>(s);
+  for (uint32_t b = tid; b < blocks; b += kReduceBlock)
+    s += static_cast<double>(partials[static_cast<size_t>(b) * ng6 + i]);
+  lds[tid] = s;
+  __syncthreads();
+  for (int w = kReduceBlock / 2; w > 0; w >>= 1) {
+    if (tid < w) lds[tid] += lds[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) grad[i] = static_cast<float>(lds[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -489,8 +508,8 @@ hipError_t launch_splat_backward(const GaussJob &j, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(64), 0, s, j.partials, blocks, ng * 6,
-                     j.mt.n_maps * 6, j.grad);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(j.mt.n_maps * 6), dim3(kReduceBlock), 0, s, j.partials,
+                     blocks, ng * 6, j.grad);
   return hipGetLastError();
 }
 
