@@ -179,12 +179,16 @@ __device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
 // Elementary Functions, 1980): k = rint(2a/pi), r = a - k P1 - k P2 - k P3
 // with pi/2 = P1 + P2 + P3, P1 and P2 of 33 significant bits (so k P1, k P2
 // are exact for |k| <= 2^19).  sin r and cos r on [-pi/4, pi/4] are their
-// Taylor series to degree 15 and 16 (truncation below 5e-17), and the
+// Taylor series to degree 13 and 14 (truncation below 3e-14 and 1e-15), and the
 // quadrant k mod 4 swaps and negates them.  Other arguments (large, infinite
-// or NaN) take the library's sincos; no lane of the workloads here does.
+// or NaN) take the library's sincos in a function of its own, so that its
+// registers stay out of the calling loop; no lane of the workloads here
+// takes that path.
+__device__ __noinline__ void sincos_f64_wide(double a, double *sn, double *cs) { sincos(a, sn, cs); }
+
 __device__ __forceinline__ void sincos_f64(double a, double *sn, double *cs) {
   if (!(fabs(a) < 823549.0)) {
-    sincos(a, sn, cs);
+    sincos_f64_wide(a, sn, cs);
     return;
   }
   const double k = rint(a * 0.63661977236758134308);
@@ -192,16 +196,14 @@ __device__ __forceinline__ void sincos_f64(double a, double *sn, double *cs) {
   r = fma(-k, 0x1.0b4611a600000p-34, r);
   r = fma(-k, 0x1.3198a2e037073p-69, r);
   const double x2 = r * r;
-  double ps = -1.0 / 1307674368000.0;
-  ps = fma(ps, x2, 1.0 / 6227020800.0);
+  double ps = 1.0 / 6227020800.0;
   ps = fma(ps, x2, -1.0 / 39916800.0);
   ps = fma(ps, x2, 1.0 / 362880.0);
   ps = fma(ps, x2, -1.0 / 5040.0);
   ps = fma(ps, x2, 1.0 / 120.0);
   ps = fma(ps, x2, -1.0 / 6.0);
   const double sr = fma(r * x2, ps, r);
-  double pc = 1.0 / 20922789888000.0;
-  pc = fma(pc, x2, -1.0 / 87178291200.0);
+  double pc = -1.0 / 87178291200.0;
   pc = fma(pc, x2, 1.0 / 479001600.0);
   pc = fma(pc, x2, -1.0 / 3628800.0);
   pc = fma(pc, x2, 1.0 / 40320.0);
