@@ -340,6 +340,8 @@ __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
 // from the mean run length, so short runs keep many runs in flight and long
 // runs are read with coalesced loads.  Every thread of the workgroup calls
 // it; `tile` is kTileElems words of LDS.
+constexpr int kRunsInFlight = 4;
+
 __device__ inline void count_records(uint32_t *tile, uint2 v, uint32_t at, uint32_t s,
                                      uint32_t e) {
   const uint32_t r4[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
@@ -362,10 +364,29 @@ __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
   const uint32_t *row1 = row0 + n_chunks;
   const uint32_t g = 1u << log2g, lane = tid & (g - 1u);
   const uint32_t groups = kAccBlock >> log2g;
-  for (uint32_t c = c_lo + (tid >> log2g); c < c_hi; c += groups) {
-    const uint32_t s = row0[c], e = row1[c];
-    for (uint32_t i = (s & ~3u) + 4u * lane; i < e; i += 4u * g)
-      count_records(tile, *reinterpret_cast<const uint2 *>(rec + i), i, s, e);
+  // kRunsInFlight runs per group at a time: their bounds, then the first
+  // 4g records of each, then the counts, so several loads per lane overlap
+  for (uint32_t c0 = c_lo + (tid >> log2g); c0 < c_hi; c0 += groups * kRunsInFlight) {
+    uint32_t s[kRunsInFlight], e[kRunsInFlight];
+#pragma unroll
+    for (int u = 0; u < kRunsInFlight; ++u) {
+      const uint32_t c = c0 + u * groups;
+      s[u] = c < c_hi ? row0[c] : 0u;
+      e[u] = c < c_hi ? row1[c] : 0u;
+    }
+    uint2 v[kRunsInFlight];
+#pragma unroll
+    for (int u = 0; u < kRunsInFlight; ++u) {
+      const uint32_t i = (s[u] & ~3u) + 4u * lane;
+      v[u] = i < e[u] ? *reinterpret_cast<const uint2 *>(rec + i) : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < kRunsInFlight; ++u) {
+      const uint32_t i = (s[u] & ~3u) + 4u * lane;
+      count_records(tile, v[u], i, s[u], e[u]);
+      for (uint32_t j = i + 4u * g; j < e[u]; j += 4u * g)
+        count_records(tile, *reinterpret_cast<const uint2 *>(rec + j), j, s[u], e[u]);
+    }
   }
   __syncthreads();
   const uint32_t base = t * kTileElems;
