@@ -340,7 +340,7 @@ __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
 // from the mean run length, so short runs keep many runs in flight and long
 // runs are read with coalesced loads.  Every thread of the workgroup calls
 // it; `tile` is kTileElems words of LDS.
-constexpr int kRunsInFlight = 4;
+constexpr int kRunsInFlight = 8;
 
 __device__ inline void count_records(uint32_t *tile, uint2 v, uint32_t at, uint32_t s,
                                      uint32_t e) {
