@@ -193,7 +193,6 @@ int pack_table(const cfs_system *s, MapTable<DIM> *mt, bool *equal) {
   *equal = (s->prob == nullptr);
   if (*equal) {
     mt->n_search = 0;
-    mt->top_step = 0;
     return CFS_OK;
   }
   // maps past the first threshold that reaches 2^32 can never be drawn
@@ -205,12 +204,6 @@ int pack_table(const cfs_system *s, MapTable<DIM> *mt, bool *equal) {
     }
   for (int i = 0; i < ns - 1; ++i) mt->thresh[i] = static_cast<uint32_t>(th[i]);
   mt->n_search = ns;
-  int step = 0;
-  if (ns > 1) {
-    step = 1;
-    while (step * 2 <= ns - 1) step *= 2;
-  }
-  mt->top_step = step;
   return CFS_OK;
 }
 

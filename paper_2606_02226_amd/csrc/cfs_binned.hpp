@@ -97,7 +97,7 @@ __device__ inline void flush_chunk(uint32_t *stage, uint32_t *cnt, uint32_t *wsu
 // count.
 template <typename real, int DIM, int FINAL, int SEL, bool GENERAL = true>
 __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_maps, int n_search,
-                                   int top_step, int flags, const Window &win, const RunArgs &ra,
+                                   int flags, const Window &win, const RunArgs &ra,
                                    const float *fparams, const BinArgs &ba, const Outputs &out,
                                    uint32_t block, uint32_t *stage, uint32_t *cnt, uint32_t *wsum) {
   if constexpr (!GENERAL) flags = 0;
@@ -122,7 +122,7 @@ __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_
       const uint32_t t = t0 + j + 1;
       if (t > T) break;
       const uint32_t u = word_of(blk, j);
-      k = select_index<SEL>(u, th, n_maps, n_search, top_step);
+      k = select_index<SEL>(u, th, n_maps, n_search);
       if (active && out.indices)
         out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
       apply_map<real, DIM>(table, k, p, flags);
@@ -219,7 +219,7 @@ __device__ inline void flush_depth_chunk(uint2 *stage, uint32_t *cnt, uint32_t *
 // and the binned depth splat (same arithmetic as the direct depth path).
 template <typename real, int SEL>
 __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_maps, int n_search,
-                                  int top_step, const Window &win, const RunArgs &ra,
+                                  const Window &win, const RunArgs &ra,
                                   const float *fparams, float near_plane, const BinArgs &ba,
                                   const Outputs &out, uint32_t block, uint2 *stage, uint32_t *cnt,
                                   uint32_t *wsum) {
@@ -240,7 +240,7 @@ __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_m
     for (int j = 0; j < 4; ++j) {
       const uint32_t t = t0 + j + 1;
       if (t > T) break;
-      k = select_index<SEL>(word_of(blk, j), th, n_maps, n_search, top_step);
+      k = select_index<SEL>(word_of(blk, j), th, n_maps, n_search);
       if (active && out.indices)
         out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
       apply_map<real, 3>(table, k, p);

@@ -60,20 +60,22 @@ __device__ __forceinline__ void initial_point(uint32_t pid, uint32_t instance,
 
 // ---------------------------------------------------------------------------
 // Selection.  Equal probabilities: k = floor(u n / 2^32) (one mul_hi).
-// Otherwise a branch-free binary search for the number of thresholds <= u
-// among the n_search - 1 finite thresholds kept in LDS.
+// Otherwise k = the number of finite thresholds <= u (the inverse CDF),
+// found with a guide table (Chen and Asau, 1974): the top kGuideBits bits of
+// u name a bucket whose entry holds lo = #{thresholds <= bucket start} and
+// hi = #{thresholds <= bucket end}; k = lo + #{i in [lo, hi) : th[i] <= u},
+// and lo == hi for all but at most n - 1 buckets.  Same result as a search
+// over all thresholds, in one LDS read for most draws.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int select_equal(uint32_t u, uint32_t n) {
   return static_cast<int>(__umulhi(u, n));
 }
 
-__device__ __forceinline__ int select_table(uint32_t u, const uint32_t *__restrict__ th,
-                                            int n_search, int top_step) {
-  int k = 0;
-  for (int step = top_step; step > 0; step >>= 1) {
-    const int probe = k + step;
-    if (probe <= n_search - 1 && th[probe - 1] <= u) k = probe;
-  }
+__device__ __forceinline__ int select_table(uint32_t u, const uint32_t *__restrict__ th) {
+  const uint32_t g = th[kMaxMaps + (u >> (32 - kGuideBits))];
+  int k = static_cast<int>(g & 0xFFFFu);
+  const int hi = static_cast<int>(g >> 16);
+  for (int i = k; i < hi; ++i) k += th[i] <= u ? 1 : 0;
   return k;
 }
 
@@ -84,15 +86,13 @@ constexpr int kSelEqual = 1;
 constexpr int kSelRuntime = 2;
 
 template <int SEL>
-__device__ __forceinline__ int select_index(uint32_t u, const uint32_t *th, int n_maps, int n_search,
-                                            int top_step) {
+__device__ __forceinline__ int select_index(uint32_t u, const uint32_t *th, int n_maps, int n_search) {
   if constexpr (SEL == kSelEqual) {
     return select_equal(u, static_cast<uint32_t>(n_maps));
   } else if constexpr (SEL == kSelTable) {
-    return select_table(u, th, n_search, top_step);
+    return select_table(u, th);
   } else {
-    return n_search == 0 ? select_equal(u, static_cast<uint32_t>(n_maps))
-                         : select_table(u, th, n_search, top_step);
+    return n_search == 0 ? select_equal(u, static_cast<uint32_t>(n_maps)) : select_table(u, th);
   }
 }
 
@@ -168,7 +168,19 @@ __device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
     }
     table[i] = v;
   }
-  for (int i = threadIdx.x; i < mt.n_search - 1; i += blockDim.x) th[i] = mt.thresh[i];
+  const int n_th = mt.n_search > 0 ? mt.n_search - 1 : 0;
+  for (int i = threadIdx.x; i < n_th; i += blockDim.x) th[i] = mt.thresh[i];
+  // guide buckets from the (uniform) thresholds in the kernel arguments
+  for (int b = threadIdx.x; b < kGuide; b += blockDim.x) {
+    const uint32_t first = static_cast<uint32_t>(b) << (32 - kGuideBits);
+    const uint32_t last = first | ((1u << (32 - kGuideBits)) - 1u);
+    uint32_t lo = 0, hi = 0;
+    for (int i = 0; i < n_th; ++i) {
+      lo += mt.thresh[i] <= first ? 1u : 0u;
+      hi += mt.thresh[i] <= last ? 1u : 0u;
+    }
+    th[kMaxMaps + b] = lo | (hi << 16);
+  }
 }
 
 // ---------------------------------------------------------------------------

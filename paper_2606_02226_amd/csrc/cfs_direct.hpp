@@ -11,7 +11,7 @@ namespace cfs {
 // GENERAL as for chaos_binned_block.
 template <typename real, int DIM, int FINAL, int SEL, bool DEPTH, bool GENERAL = true>
 __device__ void chaos_direct_point(const real *table, const uint32_t *th, int n_maps, int n_search,
-                                   int top_step, int flags, const Window &win, const RunArgs &ra,
+                                   int flags, const Window &win, const RunArgs &ra,
                                    const float *fparams, void *img, uint32_t *density,
                                    float near_plane, const Outputs &out, uint32_t n) {
   if constexpr (!GENERAL) flags = 0;
@@ -32,7 +32,7 @@ __device__ void chaos_direct_point(const real *table, const uint32_t *th, int n_
       const uint32_t t = t0 + j + 1;
       if (t > T) break;
       const uint32_t u = word_of(blk, j);
-      k = select_index<SEL>(u, th, n_maps, n_search, top_step);
+      k = select_index<SEL>(u, th, n_maps, n_search);
       if (out.indices) out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
       apply_map<real, DIM>(table, k, p, flags);
       if constexpr (DIM == 2 && FINAL != kFinalIdentity) {

@@ -7,6 +7,12 @@
 namespace cfs {
 
 constexpr int kMaxMaps = 64;
+// Selection guide: for each of the 2^kGuideBits buckets of the top bits of a
+// draw, the range of thresholds that can lie inside the bucket.  The LDS
+// threshold array holds kMaxMaps thresholds followed by the guide.
+constexpr int kGuideBits = 8;
+constexpr int kGuide = 1 << kGuideBits;
+constexpr int kThWords = kMaxMaps + kGuide;
 
 constexpr int kFinalIdentity = 0;
 constexpr int kFinalSwirl = 1;
@@ -29,7 +35,6 @@ struct MapTable {
   uint32_t thresh[kMaxMaps];
   int32_t n_maps;
   int32_t n_search;
-  int32_t top_step;  // largest power of two <= n_search - 1 (search start)
   int32_t flags;     // kFlagCircle | kFlagReuse (uniform per system)
   uint64_t circle_mask;  // bit m: map m is a circle map
 };

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_emit(const InstDesc *__rest
                                                           uint16_t *records, uint32_t *ctables,
                                                           uint32_t *tables) {
   __shared__ real table[kMaxMaps * RowStride<real, 2>::value];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   __shared__ uint32_t stage[kChunkCap];
   __shared__ uint32_t cnt[kMaxTiles];
   __shared__ uint32_t wsum[kWaves + 1];
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_emit(const InstDesc *__rest
     Outputs out{nullptr, nullptr, nullptr, d.dropped};
     for (uint32_t b = 0; b < item.n_blocks; ++b)
       chaos_binned_block<real, 2, kFinalIdentity, kSelRuntime, false>(
-          table, th, d.mt.n_maps, d.mt.n_search, d.mt.top_step, d.mt.flags, d.win, d.ra, nullptr,
+          table, th, d.mt.n_maps, d.mt.n_search, d.mt.flags, d.win, d.ra, nullptr,
           ba, out,
           item.first_block + b, stage, cnt, wsum);
     __syncthreads();
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_direct(const InstDesc *__re
                                                             const EmitItem *__restrict__ items,
                                                             uint32_t n_items, uint32_t *queue) {
   __shared__ real table[kMaxMaps * RowStride<real, 2>::value];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   __shared__ uint32_t slot;
   for (;;) {
     const uint32_t it = pop_item(queue, &slot);
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_direct(const InstDesc *__re
     Outputs out{nullptr, nullptr, nullptr, d.dropped};
     for (uint32_t b = 0; b < item.n_blocks; ++b)
       chaos_direct_point<real, 2, kFinalIdentity, kSelRuntime, false, false>(
-          table, th, d.mt.n_maps, d.mt.n_search, d.mt.top_step, d.mt.flags, d.win, d.ra, nullptr,
+          table, th, d.mt.n_maps, d.mt.n_search, d.mt.flags, d.win, d.ra, nullptr,
           d.img,
           nullptr, 0.0f, out, (item.first_block + b) * kBinBlock + threadIdx.x);
     __syncthreads();

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_binned(MapTable<DIM> mt, Wi
                                                             RunArgs ra, FinalArgs fa, BinArgs ba,
                                                             Outputs out) {
   __shared__ real table[kMaxMaps * RowStride<real, DIM>::value];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   __shared__ uint32_t stage[kChunkCap];
   __shared__ uint32_t cnt[kMaxTiles];
   __shared__ uint32_t wsum[kWaves + 1];
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_binned(MapTable<DIM> mt, Wi
   for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
   __syncthreads();
   chaos_binned_block<real, DIM, FINAL, EQUAL, GENERAL>(table, th, mt.n_maps, mt.n_search,
-                                                       mt.top_step, mt.flags, win, ra, fa.p, ba,
+                                                       mt.flags, win, ra, fa.p, ba,
                                                        out, blockIdx.x, stage, cnt, wsum);
 }
 
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_depth_binned(MapTable<3> mt
                                                                   float near_plane, BinArgs ba,
                                                                   Outputs out) {
   __shared__ real table[kMaxMaps * RowStride<real, 3>::value];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   __shared__ uint2 stage[kDCap];
   __shared__ uint32_t cnt[kMaxTiles];
   __shared__ uint32_t wsum[kWaves + 1];
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_depth_binned(MapTable<3> mt
   for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
   __syncthreads();
   chaos_depth_block<real, EQUAL ? kSelEqual : kSelTable>(table, th, mt.n_maps, mt.n_search,
-                                                         mt.top_step, win, ra, fa.p, near_plane,
+                                                         win, ra, fa.p, near_plane,
                                                          ba, out, blockIdx.x, stage, cnt, wsum);
 }
 

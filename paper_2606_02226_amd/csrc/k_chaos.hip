@@ -19,11 +19,11 @@ __global__ __launch_bounds__(kChaosBlock) void k_chaos(MapTable<DIM> mt, Window 
                                                        uint32_t *density, float near_plane,
                                                        Outputs out) {
   __shared__ real table[kMaxMaps * RowStride<real, DIM>::value];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   load_table<real, DIM>(mt, table, th);
   __syncthreads();
   chaos_direct_point<real, DIM, FINAL, EQUAL, DEPTH, GENERAL>(
-      table, th, mt.n_maps, mt.n_search, mt.top_step, mt.flags, win, ra, fa.p, img, density,
+      table, th, mt.n_maps, mt.n_search, mt.flags, win, ra, fa.p, img, density,
       near_plane, out, blockIdx.x * kChaosBlock + threadIdx.x);
 }
 

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kGBlock) void k_splat_emit(MapTable<2> mt, RunArgs 
                                                         GaussBin gb, GaussCkpt ck,
                                                         unsigned long long *dropped_out) {
   __shared__ float table[kMaxMaps * 8];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   __shared__ float2 stage[kGCap];
   __shared__ uint32_t cnt[kGMaxTiles];
   __shared__ uint32_t wsum[kGWaves + 1];
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kGBlock) void k_splat_emit(MapTable<2> mt, RunArgs 
       if constexpr (EQUAL)
         k = select_equal(u, static_cast<uint32_t>(mt.n_maps));
       else
-        k = select_table(u, th, mt.n_search, mt.top_step);
+        k = select_table(u, th);
       apply_map<float, 2>(table, k, p);
       if (active && ck.ckpt && t < T && t % ck.every == 0)
         reinterpret_cast<float2 *>(ck.ckpt)[static_cast<size_t>(t / ck.every) * ck.stride + n] =
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, R
                                                                const float *__restrict__ dLdD,
                                                                GaussCkpt ck, float *partials) {
   __shared__ float table[kMaxMaps * 8];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   __shared__ float red[kGBwdBlock / 64][NG * 6];
   load_table<float, 2>(mt, table, th);
   __syncthreads();
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, R
         if constexpr (EQUAL)
           k = select_equal(u, static_cast<uint32_t>(mt.n_maps));
         else
-          k = select_table(u, th, mt.n_search, mt.top_step);
+          k = select_table(u, th);
         apply_map<float, 2>(table, k, p);
         px[m] = p[0];
         py[m] = p[1];

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kSceneBlock) void k_scene(MapTable<2> mt, Window wi
                                                        SceneArgs sc, uint32_t *img,
                                                        unsigned long long *dropped_out) {
   __shared__ real table[kMaxMaps * RowStride<real, 2>::value];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   load_table<real, 2>(mt, table, th);
   __syncthreads();
   const uint32_t n = blockIdx.x * kSceneBlock + threadIdx.x;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kSceneBlock) void k_scene(MapTable<2> mt, Window wi
     for (int j = 0; j < 4; ++j) {
       const uint32_t t = t0 + j + 1;
       if (t > T) break;
-      const int k = select_index<SEL>(word_of(blk, j), th, mt.n_maps, mt.n_search, mt.top_step);
+      const int k = select_index<SEL>(word_of(blk, j), th, mt.n_maps, mt.n_search);
       apply_map<real, 2>(table, k, p, mt.flags);
       if (t <= B) continue;
       const uint32_t cu = word_of(cblk, j);
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBinBlock) void k_scene_binned(MapTable<2> mt, Wind
                                                             RunArgs ra, SceneArgs sc, BinArgs ba,
                                                             unsigned long long *dropped_out) {
   __shared__ real table[kMaxMaps * RowStride<real, 2>::value];
-  __shared__ uint32_t th[kMaxMaps];
+  __shared__ uint32_t th[kThWords];
   __shared__ uint32_t stage[kChunkCap];
   __shared__ uint32_t cnt[kMaxTiles];
   __shared__ uint32_t wsum[kWaves + 1];
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBinBlock) void k_scene_binned(MapTable<2> mt, Wind
     for (int j = 0; j < 4; ++j) {
       const uint32_t t = t0 + j + 1;
       if (t > T) break;
-      const int k = select_index<SEL>(word_of(blk, j), th, mt.n_maps, mt.n_search, mt.top_step);
+      const int k = select_index<SEL>(word_of(blk, j), th, mt.n_maps, mt.n_search);
       apply_map<real, 2>(table, k, p, mt.flags);
       if (t <= B) continue;
       const uint32_t cu = word_of(cblk, j);
