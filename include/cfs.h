@@ -289,8 +289,10 @@ int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
               float sigma_px, float *ckpt, int32_t ckpt_every, void *workspace,
               size_t workspace_bytes, void *stream);
 
-/* Workspace in bytes for cfs_splat_backward. */
-size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run);
+/* Workspace in bytes for cfs_splat_backward with this system, run, density
+ * image and sigma (0 on invalid arguments). */
+size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run,
+                                    const cfs_image *img, float sigma_px);
 
 /* Differentiable form, adjoint: given dL/dD (device float [H][W], the
  * upstream gradient of the density that cfs_splat produced) and that call's
@@ -303,6 +305,10 @@ size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run);
  * workgroup, and a fixed-order two-level FP64 sum over workgroups; no
  * floating-point atomics).  ckpt must be
  * the forward's checkpoints for the same system, run and ckpt_every (1..16).
+ * The splat gradients s_t are computed per image tile from an LDS copy of
+ * dL/dD over the splats' records (recomputed from the random streams), then
+ * each point's sweep reads them.  workspace: device,
+ * cfs_splat_backward_workspace() bytes, 256-byte aligned.
  * Systems of at most 8 maps. */
 int cfs_splat_backward(const cfs_system *sys, const cfs_run *run,
                        const cfs_image *img, float sigma_px,

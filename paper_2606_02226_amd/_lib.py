@@ -108,7 +108,8 @@ def load():
     lib.cfs_splat_workspace.restype = C.c_size_t
     lib.cfs_splat.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun), C.POINTER(CfsImage),
                               C.c_float, P, C.c_int32, P, C.c_size_t, P]
-    lib.cfs_splat_backward_workspace.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun)]
+    lib.cfs_splat_backward_workspace.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun),
+                                                 C.POINTER(CfsImage), C.c_float]
     lib.cfs_splat_backward_workspace.restype = C.c_size_t
     lib.cfs_splat_backward.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun),
                                        C.POINTER(CfsImage), C.c_float, P, P, C.c_int32, P,

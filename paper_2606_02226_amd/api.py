@@ -270,15 +270,19 @@ def splat(system, run, image, sigma_px, *, ckpt=None, ckpt_every=8, workspace=No
 
 
 def splat_backward(system, run, image, sigma_px, dL_dD, ckpt, ckpt_every=8, grad=None,
-                   stream=None):
+                   workspace=None, stream=None):
     """Adjoint of the Gaussian splat (cfs_splat_backward): returns the float32
     device gradient [n_maps][6] = (a00, a01, a10, a11, b0, b1)."""
     lib = _lib.load()
     sysc = system if isinstance(system, System) else System(system)
     runc = run_struct(run, "f32")
-    need = int(lib.cfs_splat_backward_workspace(C.byref(sysc.struct), C.byref(runc)))
+    need = int(lib.cfs_splat_backward_workspace(C.byref(sysc.struct), C.byref(runc),
+                                                C.byref(image.struct), C.c_float(sigma_px)))
     dev = dL_dD.device
-    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if workspace is not None and workspace.numel() >= need:
+        ws = workspace
+    else:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     if grad is None:
         grad = torch.empty((sysc.n_maps, 6), dtype=torch.float32, device=dev)
     g = dL_dD.contiguous()

@@ -131,11 +131,38 @@ extern "C" int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_im
   return CFS_OK;
 }
 
-extern "C" size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run) {
-  if (validate_system(sys) || validate_run(run)) return 0;
+namespace {
+
+// Backward workspace layout: the gradient partials of every sweep workgroup
+// of the run, then, reused by every launch slice, the slice's records, their
+// ids, the two run tables and the splat gradients S.
+struct BwdLayout {
+  size_t partials, records, ids, table, s, total;
+};
+
+BwdLayout bwd_layout(const cfs_system *sys, const cfs_run *run, const cfs_image *img) {
+  BwdLayout l{};
   const uint32_t blocks = (run->n_points + kGBwdBlock - 1) / kGBwdBlock;
   const int ng = sys->n_maps <= 4 ? 4 : 8;
-  return align_up(static_cast<size_t>(std::max<uint32_t>(blocks, 1)) * ng * 6 * sizeof(float));
+  l.partials = align_up(static_cast<size_t>(std::max<uint32_t>(blocks, 1)) * ng * 6 * sizeof(float));
+  if (run->n_iters > run->burn_in && run->n_points > 0) {
+    const uint32_t slice = gauss_slice(run);
+    const GaussPlan p = gauss_plan(slice, run->n_iters, run->burn_in, img->width, img->height);
+    l.records = align_up(p.records_bytes);
+    l.ids = align_up(static_cast<size_t>(p.n_chunks) * kGCap * sizeof(uint16_t));
+    l.table = align_up(p.table_bytes);
+    l.s = align_up(static_cast<size_t>(slice) * (run->n_iters - run->burn_in) * sizeof(float2));
+  }
+  l.total = l.partials + l.records + l.ids + 2 * l.table + l.s;
+  return l;
+}
+
+}  // namespace
+
+extern "C" size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run,
+                                               const cfs_image *img, float sigma_px) {
+  if (validate_gauss(sys, run, img, sigma_px)) return 0;
+  return bwd_layout(sys, run, img).total;
 }
 
 extern "C" int cfs_splat_backward(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
@@ -152,24 +179,50 @@ extern "C" int cfs_splat_backward(const cfs_system *sys, const cfs_run *run, con
   if ((reinterpret_cast<uintptr_t>(dL_dD) | reinterpret_cast<uintptr_t>(grad)) % 4 ||
       reinterpret_cast<uintptr_t>(ckpt) % 8)
     return fail(CFS_E_INVALID, "misaligned dL_dD, ckpt or grad");
-  const size_t need = cfs_splat_backward_workspace(sys, run);
-  if (!workspace || workspace_bytes < need)
-    return fail(CFS_E_WORKSPACE, "cfs_splat_backward needs %zu bytes of workspace, got %zu", need,
-                workspace ? workspace_bytes : static_cast<size_t>(0));
+  const BwdLayout l = bwd_layout(sys, run, img);
+  if (!workspace || workspace_bytes < l.total)
+    return fail(CFS_E_WORKSPACE, "cfs_splat_backward needs %zu bytes of workspace, got %zu",
+                l.total, workspace ? workspace_bytes : static_cast<size_t>(0));
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(CFS_E_WORKSPACE, "workspace must be 256-byte aligned");
   GaussJob job;
   std::memset(&job, 0, sizeof job);
   rc = pack_table<2>(sys, &job.mt, &job.equal);
   if (rc) return rc;
-  job.ra = make_run_args(run);
   job.gp = make_gauss_params(run, img, sigma_px);
-  job.ck.ckpt = const_cast<float *>(ckpt);
-  job.ck.every = ckpt_every;
-  job.ck.stride = run->n_points;
   job.dLdD = dL_dD;
-  job.partials = static_cast<float *>(workspace);
   job.grad = grad;
-  return device_status(launch_splat_backward(job, static_cast<hipStream_t>(stream)),
-                       "cfs_splat_backward");
+  char *ws = static_cast<char *>(workspace);
+  job.partials = reinterpret_cast<float *>(ws);
+  char *p = ws + l.partials;
+  job.gb.records = reinterpret_cast<float2 *>(p);
+  job.gb.ids = reinterpret_cast<uint16_t *>(p + l.records);
+  job.gb.chunk_start = reinterpret_cast<uint32_t *>(p + l.records + l.ids);
+  job.gb.tile_start = reinterpret_cast<uint32_t *>(p + l.records + l.ids + l.table);
+  job.S = reinterpret_cast<float2 *>(p + l.records + l.ids + 2 * l.table);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const RunArgs ra = make_run_args(run);
+  const bool splats = run->n_iters > run->burn_in;
+  const uint32_t slice = gauss_slice(run);
+  for (uint32_t done = 0; done < run->n_points; done += slice) {
+    const uint32_t pts = std::min(slice, run->n_points - done);
+    GaussJob j = job;
+    j.ra = ra;
+    j.ra.n_points = pts;
+    j.ra.point_offset = run->point_offset + done;
+    const GaussPlan gpl = gauss_plan(pts, run->n_iters, run->burn_in, img->width, img->height);
+    j.gb.n_chunks = splats ? gpl.n_chunks : 0;
+    j.gb.flushes = gpl.flushes;
+    j.gb.n_tiles = gpl.n_tiles;
+    j.ck.ckpt = const_cast<float *>(ckpt) + 2 * static_cast<size_t>(done);
+    j.ck.every = ckpt_every;
+    j.ck.stride = run->n_points;
+    // slices are multiples of the sweep's workgroup size
+    rc = device_status(launch_splat_backward_slice(j, done / kGBwdBlock, s), "cfs_splat_backward");
+    if (rc) return rc;
+  }
+  const uint32_t blocks = (run->n_points + kGBwdBlock - 1) / kGBwdBlock;
+  return device_status(launch_grad_reduce(job, blocks, s), "cfs_splat_backward");
 }
 
 extern "C" size_t cfs_l2_loss_workspace(uint64_t n) {

@@ -116,6 +116,7 @@ struct GaussParams {
 
 struct GaussBin {
   float2 *records;       // [n_chunks][kGCap] pixel coordinates, runs by tile
+  uint16_t *ids;         // backward only: each record's slot before sorting (or null)
   uint32_t *chunk_start; // [n_chunks][n_tiles + 1] as the chunks write them
   uint32_t *tile_start;  // [n_tiles + 1][n_chunks] transposed for the accumulate
   uint32_t n_chunks, flushes, n_tiles;

@@ -84,8 +84,12 @@ __device__ uint32_t gblock_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsu
   return total;
 }
 
-__device__ void gauss_flush(float2 *stage, uint32_t *cnt, uint32_t *wsum, int used, uint32_t chunk,
-                            const GaussParams &gp, const GaussBin &gb) {
+// IDS: also write, per record, its slot in the stage before sorting
+// (slot * kGBlock + lane), from which the adjoint recovers the point and the
+// iteration of every record.
+template <bool IDS>
+__device__ void gauss_flush(float2 *stage, uint16_t *idstage, uint32_t *cnt, uint32_t *wsum, int used,
+                            uint32_t chunk, const GaussParams &gp, const GaussBin &gb) {
   __syncthreads();
   const int tid = threadIdx.x;
   float2 e[kGSlots];
@@ -103,21 +107,28 @@ __device__ void gauss_flush(float2 *stage, uint32_t *cnt, uint32_t *wsum, int us
   for (uint32_t t = tid; t <= gb.n_tiles; t += kGBlock) row[t] = base + (t < gb.n_tiles ? cnt[t] : total);
 #pragma unroll
   for (int i = 0; i < kGSlots; ++i)
-    if (tl[i] != kGInvalid) stage[cnt[tl[i]] + r[i]] = e[i];
+    if (tl[i] != kGInvalid) {
+      stage[cnt[tl[i]] + r[i]] = e[i];
+      if constexpr (IDS) idstage[cnt[tl[i]] + r[i]] = static_cast<uint16_t>(i * kGBlock + tid);
+    }
   __syncthreads();
-  for (uint32_t i = tid; i < total; i += kGBlock) gb.records[static_cast<size_t>(base) + i] = stage[i];
+  for (uint32_t i = tid; i < total; i += kGBlock) {
+    gb.records[static_cast<size_t>(base) + i] = stage[i];
+    if constexpr (IDS) gb.ids[static_cast<size_t>(base) + i] = idstage[i];
+  }
   __syncthreads();
   for (uint32_t t = tid; t < gb.n_tiles; t += kGBlock) cnt[t] = 0u;
   __syncthreads();
 }
 
-template <bool EQUAL>
+template <bool EQUAL, bool IDS>
 __global__ __launch_bounds__(kGBlock) void k_splat_emit(MapTable<2> mt, RunArgs ra, GaussParams gp,
                                                         GaussBin gb, GaussCkpt ck,
                                                         unsigned long long *dropped_out) {
   __shared__ float table[kMaxMaps * 8];
   __shared__ uint32_t th[kThWords];
   __shared__ float2 stage[kGCap];
+  __shared__ uint16_t idstage[IDS ? kGCap : 1];
   __shared__ uint32_t cnt[kGMaxTiles];
   __shared__ uint32_t wsum[kGWaves + 1];
   const int tid = threadIdx.x;
@@ -168,14 +179,14 @@ __global__ __launch_bounds__(kGBlock) void k_splat_emit(MapTable<2> mt, RunArgs 
         }
         stage[slot * kGBlock + tid] = rec;
         if (++slot == kGSlots) {
-          gauss_flush(stage, cnt, wsum, slot, chunk, gp, gb);
+          gauss_flush<IDS>(stage, idstage, cnt, wsum, slot, chunk, gp, gb);
           slot = 0;
           ++chunk;
         }
       }
     }
   }
-  if (slot > 0) gauss_flush(stage, cnt, wsum, slot, chunk, gp, gb);
+  if (slot > 0) gauss_flush<IDS>(stage, idstage, cnt, wsum, slot, chunk, gp, gb);
   if (active && dropped_out && dropped)
     __hip_atomic_fetch_add(dropped_out, static_cast<unsigned long long>(dropped), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -263,15 +274,13 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
-template <int TAPS>
-__device__ __forceinline__ void splat_grad(float px, float py, const GaussParams &gp,
-                                           const float *__restrict__ G, float *sx, float *sy) {
-  *sx = 0.0f;
-  *sy = 0.0f;
-  const float x = (px - gp.lo[0]) * gp.scale[0];
-  const float y = (py - gp.lo[1]) * gp.scale[1];
-  const float lim = gp.R + 16.0f;
-  if (!(x > -lim && x < gp.width + lim && y > -lim && y < gp.height + lim)) return;
+// dL/dx, dL/dy (in pixels, before the chain to positions) of one splat at
+// pixel coordinates (x, y): the taps' weights g and derivatives dg against
+// the upstream gradient G, read through `at(row, col)` for the taps that
+// have a weight or a derivative.
+template <int TAPS, typename GAt>
+__device__ __forceinline__ void splat_grad_px(float x, float y, const GaussParams &gp, GAt at,
+                                              float *ax_out, float *ay_out) {
   const int i0 = first_tap(x, gp.R), j0 = first_tap(y, gp.R);
   float gx[TAPS], dgx[TAPS], gy[TAPS], dgy[TAPS];
 #pragma unroll
@@ -293,28 +302,75 @@ __device__ __forceinline__ void splat_grad(float px, float py, const GaussParams
 #pragma unroll
   for (int b = 0; b < TAPS; ++b) {
     if (gy[b] == 0.0f && dgy[b] == 0.0f) continue;
-    const float *row = G + static_cast<size_t>(j0 + b) * gp.width;
     float sg = 0.0f, sdg = 0.0f;
 #pragma unroll
     for (int a = 0; a < TAPS; ++a) {
       if (gx[a] == 0.0f && dgx[a] == 0.0f) continue;
-      const float v = row[i0 + a];
+      const float v = at(j0 + b, i0 + a);
       sg += v * gx[a];
       sdg += v * dgx[a];
     }
     ax += gy[b] * sdg;
     ay += dgy[b] * sg;
   }
-  // d(dx)/dp_x = -scale_x, d(dy)/dp_y = -scale_y
-  *sx = -ax * gp.scale[0] * gp.weight;
-  *sy = -ay * gp.scale[1] * gp.weight;
+  *ax_out = ax;
+  *ay_out = ay;
 }
 
-template <int TAPS, int NG, bool EQUAL>
+// Per record of one tile and chunk range: the gradient of the loss with
+// respect to the splatted position, from an LDS copy of the tile's upstream
+// gradient with the same halo as the forward accumulate, written to
+// S[iteration - B - 1][point] (points of the launch slice).  One workgroup
+// per (tile, chunk range); groups of 2^log2g lanes per run.
+template <int TAPS>
+__global__ __launch_bounds__(kGAccBlock) void k_splat_grad_tiles(
+    const float2 *__restrict__ rec, const uint16_t *__restrict__ ids,
+    const uint32_t *__restrict__ tile_start, uint32_t n_chunks, uint32_t flushes, uint32_t points,
+    GaussParams gp, uint32_t parts, uint32_t log2g, const float *__restrict__ G,
+    float2 *__restrict__ S) {
+  constexpr int H = kGTile + TAPS - 1;
+  __shared__ float g[H * H];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t item = xcd_item(blockIdx.x, gridDim.x);
+  const uint32_t t = item / parts, part = item % parts;
+  const uint32_t c_lo = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * part / parts);
+  const uint32_t c_hi = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * (part + 1) / parts);
+  const int tx = t % gp.tiles_x, ty = t / gp.tiles_x;
+  const int x0 = tx * kGTile, y0 = ty * kGTile;
+  for (uint32_t i = tid; i < H * H; i += kGAccBlock) {
+    const int px = x0 + static_cast<int>(i % H), py = y0 + static_cast<int>(i / H);
+    g[i] = (px < gp.width && py < gp.height) ? G[static_cast<size_t>(py) * gp.width + px] : 0.0f;
+  }
+  __syncthreads();
+  // every tap with a weight lies in [x0, x0 + H) x [y0, y0 + H) (records are
+  // binned by their first tap; taps left of or above the image have none)
+  auto at = [&](int row, int col) { return g[(row - y0) * H + (col - x0)]; };
+  const float cx = -gp.scale[0] * gp.weight, cy = -gp.scale[1] * gp.weight;
+  const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
+  const uint32_t *row1 = row0 + n_chunks;
+  const uint32_t gsz = 1u << log2g, lane = tid & (gsz - 1u), groups = kGAccBlock >> log2g;
+  for (uint32_t c = c_lo + (tid >> log2g); c < c_hi; c += groups) {
+    const uint32_t s = row0[c], e = row1[c];
+    const uint32_t block = c / flushes, flush = c % flushes;
+    for (uint32_t i = s + lane; i < e; i += gsz) {
+      const float2 r = rec[i];
+      const uint32_t slot = ids[i];
+      const uint32_t n = block * kGBlock + slot % kGBlock;
+      const uint32_t tt = flush * kGSlots + slot / kGBlock;
+      float ax, ay;
+      splat_grad_px<TAPS>(r.x, r.y, gp, at, &ax, &ay);
+      S[static_cast<size_t>(tt) * points + n] = make_float2(ax * cx, ay * cy);
+    }
+  }
+}
+
+// The adjoint sweep of each point of a launch slice, with the splat
+// gradients S[t - B - 1][point] already computed per tile.
+template <int NG, bool EQUAL>
 __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, RunArgs ra,
-                                                               GaussParams gp,
-                                                               const float *__restrict__ dLdD,
-                                                               GaussCkpt ck, float *partials) {
+                                                               const float2 *__restrict__ S,
+                                                               GaussCkpt ck, float *partials,
+                                                               uint32_t block_offset) {
   __shared__ float table[kMaxMaps * 8];
   __shared__ uint32_t th[kThWords];
   __shared__ float red[kGBwdBlock / 64][NG * 6];
@@ -371,7 +427,11 @@ __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, R
         if (static_cast<uint32_t>(m) > len) continue;
         const uint32_t t = t_start + m;
         float s0 = 0.0f, s1 = 0.0f;
-        if (t > B) splat_grad<TAPS>(px[m], py[m], gp, dLdD, &s0, &s1);
+        if (t > B) {
+          const float2 sv = S[static_cast<size_t>(t - B - 1) * ra.n_points + n];
+          s0 = sv.x;
+          s1 = sv.y;
+        }
         float c0 = 0.0f, c1 = 0.0f;
         if (k_next >= 0) {
           const float *A = table + k_next * 8;  // a00 a01 a10 a11: A^T lam
@@ -411,7 +471,7 @@ __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, R
   if (tid < NG * 6) {
     float s = 0.0f;
     for (int ww = 0; ww < kGBwdBlock / 64; ++ww) s += red[ww][tid];
-    partials[static_cast<size_t>(blockIdx.x) * (NG * 6) + tid] = s;
+    partials[static_cast<size_t>(block_offset + blockIdx.x) * (NG * 6) + tid] = s;
   }
 }
 
@@ -452,22 +512,10 @@ GaussPlan gauss_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, int wi
   return gp;
 }
 
-hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
-  if (j.ra.n_points == 0 || j.gb.n_chunks == 0) return hipSuccess;
-  const uint32_t blocks = (j.ra.n_points + kGBlock - 1) / kGBlock;
-  if (j.equal)
-    hipLaunchKernelGGL(k_splat_emit<true>, dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp, j.gb,
-                       j.ck, j.dropped);
-  else
-    hipLaunchKernelGGL(k_splat_emit<false>, dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp, j.gb,
-                       j.ck, j.dropped);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = launch_transpose(j.gb.chunk_start, j.gb.tile_start, j.gb.n_chunks, j.gb.n_tiles + 1, s);
-  if (e != hipSuccess) return e;
-  // lanes per run from the mean run length (one record per lane), and enough
-  // workgroups per tile for eight small workgroups per CU while each keeps
-  // one pass of groups
+// Per-tile kernels' launch shape: lanes per run from the mean run length (one
+// record per lane), and enough workgroups per tile for eight small
+// workgroups per CU while each keeps one pass of groups.
+static void gauss_tile_shape(const GaussJob &j, uint32_t *parts_out, uint32_t *lg_out) {
   const uint64_t runs = static_cast<uint64_t>(j.gb.n_chunks) * j.gb.n_tiles;
   const uint64_t mean = runs ? static_cast<uint64_t>(j.ra.n_points) * (j.ra.n_iters - j.ra.burn_in) / runs : 0;
   uint32_t lg = 0;
@@ -477,6 +525,31 @@ hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
   const uint32_t pmax = j.gb.n_chunks / groups > 1 ? j.gb.n_chunks / groups : 1;
   if (parts > pmax) parts = pmax;
   if (parts < 1) parts = 1;
+  *parts_out = parts;
+  *lg_out = lg;
+}
+
+template <bool IDS>
+static hipError_t launch_emit(const GaussJob &j, const GaussCkpt &ck, unsigned long long *dropped,
+                              hipStream_t s) {
+  const uint32_t blocks = (j.ra.n_points + kGBlock - 1) / kGBlock;
+  if (j.equal)
+    hipLaunchKernelGGL((k_splat_emit<true, IDS>), dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp,
+                       j.gb, ck, dropped);
+  else
+    hipLaunchKernelGGL((k_splat_emit<false, IDS>), dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp,
+                       j.gb, ck, dropped);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_transpose(j.gb.chunk_start, j.gb.tile_start, j.gb.n_chunks, j.gb.n_tiles + 1, s);
+}
+
+hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
+  if (j.ra.n_points == 0 || j.gb.n_chunks == 0) return hipSuccess;
+  hipError_t e = launch_emit<false>(j, j.ck, j.dropped, s);
+  if (e != hipSuccess) return e;
+  uint32_t parts, lg;
+  gauss_tile_shape(j, &parts, &lg);
   if (j.gp.taps <= 6)
     hipLaunchKernelGGL(k_splat_accumulate<6>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
                        j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, parts, lg, j.dens);
@@ -486,28 +559,50 @@ hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int TAPS, int NG>
-static void launch_bwd_typed(const GaussJob &j, uint32_t blocks, hipStream_t s) {
+template <int NG>
+static void launch_sweep(const GaussJob &j, uint32_t block_offset, hipStream_t s) {
+  const uint32_t blocks = (j.ra.n_points + kGBwdBlock - 1) / kGBwdBlock;
   if (j.equal)
-    hipLaunchKernelGGL((k_splat_backward<TAPS, NG, true>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt,
-                       j.ra, j.gp, j.dLdD, j.ck, j.partials);
+    hipLaunchKernelGGL((k_splat_backward<NG, true>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt, j.ra,
+                       j.S, j.ck, j.partials, block_offset);
   else
-    hipLaunchKernelGGL((k_splat_backward<TAPS, NG, false>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt,
-                       j.ra, j.gp, j.dLdD, j.ck, j.partials);
+    hipLaunchKernelGGL((k_splat_backward<NG, false>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt, j.ra,
+                       j.S, j.ck, j.partials, block_offset);
 }
 
-hipError_t launch_splat_backward(const GaussJob &j, hipStream_t s) {
-  const uint32_t blocks = (j.ra.n_points + kGBwdBlock - 1) / kGBwdBlock;
-  const int ng = j.mt.n_maps <= 4 ? 4 : 8;
-  if (blocks > 0) {
-    if (j.gp.taps <= 6) {
-      if (ng == 4) launch_bwd_typed<6, 4>(j, blocks, s); else launch_bwd_typed<6, 8>(j, blocks, s);
-    } else {
-      if (ng == 4) launch_bwd_typed<16, 4>(j, blocks, s); else launch_bwd_typed<16, 8>(j, blocks, s);
-    }
-    hipError_t e = hipGetLastError();
+hipError_t launch_splat_backward_slice(const GaussJob &j, uint32_t block_offset, hipStream_t s) {
+  if (j.ra.n_points == 0) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (j.gb.n_chunks) {
+    // the slice's records again, with their ids, then the splat gradients per tile
+    const GaussCkpt none{nullptr, 1, 0};
+    e = launch_emit<true>(j, none, nullptr, s);
+    if (e != hipSuccess) return e;
+    const size_t words = static_cast<size_t>(j.ra.n_points) * (j.ra.n_iters - j.ra.burn_in) * 2;
+    e = launch_clear_u32(reinterpret_cast<uint32_t *>(j.S), words, s);
+    if (e != hipSuccess) return e;
+    uint32_t parts, lg;
+    gauss_tile_shape(j, &parts, &lg);
+    if (j.gp.taps <= 6)
+      hipLaunchKernelGGL(k_splat_grad_tiles<6>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
+                         j.gb.records, j.gb.ids, j.gb.tile_start, j.gb.n_chunks, j.gb.flushes,
+                         j.ra.n_points, j.gp, parts, lg, j.dLdD, j.S);
+    else
+      hipLaunchKernelGGL(k_splat_grad_tiles<16>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
+                         j.gb.records, j.gb.ids, j.gb.tile_start, j.gb.n_chunks, j.gb.flushes,
+                         j.ra.n_points, j.gp, parts, lg, j.dLdD, j.S);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  if (j.mt.n_maps <= 4)
+    launch_sweep<4>(j, block_offset, s);
+  else
+    launch_sweep<8>(j, block_offset, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const GaussJob &j, uint32_t blocks, hipStream_t s) {
+  const int ng = j.mt.n_maps <= 4 ? 4 : 8;
   hipLaunchKernelGGL(k_grad_reduce, dim3(j.mt.n_maps * 6), dim3(kReduceBlock), 0, s, j.partials,
                      blocks, ng * 6, j.grad);
   return hipGetLastError();

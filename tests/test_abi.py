@@ -212,7 +212,7 @@ def test_workspace_queries_on_invalid_input(L):
     lib = L.load()
     assert lib.cfs_chaos_game_workspace(None, None, None) == 0
     assert lib.cfs_splat_workspace(None, None, None, 1.0) == 0
-    assert lib.cfs_splat_backward_workspace(None, None) == 0
+    assert lib.cfs_splat_backward_workspace(None, None, None, 1.0) == 0
 
 
 def test_bad_map_kind(L):
