@@ -241,7 +241,7 @@ def main():
     ap.add_argument("--precision", choices=["f32", "f64"], default="f64")
     ap.add_argument("--points-log2", type=int, default=24)
     ap.add_argument("--splat-path", choices=["auto", "direct", "binned"], default="auto")
-    ap.add_argument("--cpu-sample-log2", type=int, default=21)
+    ap.add_argument("--cpu-sample-log2", type=int, default=23)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--calibration-copy", action="store_true",

@@ -18,7 +18,9 @@ namespace cfs {
 __device__ __forceinline__ uint32_t pop_item(uint32_t *queue, uint32_t *slot) {
   if (threadIdx.x == 0) *slot = atomicAdd(queue, 1u);
   __syncthreads();
-  const uint32_t it = *slot;
+  // the same value in every lane: keep it (and the item and descriptor loads
+  // indexed by it) on the scalar unit
+  const uint32_t it = __builtin_amdgcn_readfirstlane(*slot);
   __syncthreads();
   return it;
 }

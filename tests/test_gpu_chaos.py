@@ -498,3 +498,31 @@ def test_timing_hook_phases(api):
     assert np.all(ph >= 0) and ph[0, 0] > 0 and ph[1, 0] > 0
     assert ph[1, 1] < 0.05 and ph[1, 2] < 0.05
     assert api.timing_read().shape == (0, 3)
+
+
+@pytest.mark.parametrize("case", ["dirichlet64", "bucket_edges", "tiny"])
+def test_selection_guide_cases(api, orc, case):
+    # the guide-table selection against the oracle's plain inverse CDF:
+    # 64 maps (several thresholds per guide bucket), thresholds exactly on
+    # bucket boundaries (multiples of 2^24), and clusters of tiny probabilities
+    rng = np.random.default_rng(21)
+    if case == "dirichlet64":
+        n = 64
+        prob = rng.dirichlet(np.ones(n) * 0.3)
+    elif case == "bucket_edges":
+        n = 8
+        prob = np.array([1, 3, 5, 7, 64, 32, 16, 128], np.float64) / 256.0
+    else:
+        n = 12
+        prob = np.full(n, 1e-9)
+        prob[[0, 5, 11]] = (1.0 - 9e-9) / 3
+    A = np.stack([np.eye(2) * 0.3] * n).astype(np.float32)
+    b = rng.uniform(0, 0.7, size=(n, 2)).astype(np.float32)
+    system = W._system(A, b, prob=prob)
+    run = {"seed": 12345, "instance": 1, "n_points": 20000, "point_offset": 0,
+           "n_iters": 32, "burn_in": 8}
+    img = {"kind": "u32_count", "width": 64, "height": 64, "channels": 1,
+           "lo": [0, 0], "hi": [1, 1]}
+    got = run_gpu(api, None, "f32", want_indices=True, system=system, run=run, image=img)
+    ref = orc.chaos_count(system, run, img, want_indices=True)
+    assert np.array_equal(got["indices"], ref["indices"])

@@ -137,3 +137,13 @@ def test_translation_gradient_closed_form(orc, which):
         fd = (lin(sp) - lin(sm)) / (2 * h)
         got = grad[:, 0].sum()
     assert abs(got - fd) <= 1e-4 * max(1.0, abs(fd)), (got, fd)
+
+
+def test_l2_loss_hand_values(orc):
+    # L = sum (D - D*)^2 and dL/dD = 2 (D - D*), checked on values worked by hand
+    loss, grad = orc.l2_loss(np.array([1.0, 2.0, 0.5], np.float32),
+                             np.array([0.0, 3.0, 0.5], np.float32))
+    assert loss == 2.0
+    assert np.array_equal(grad, [2.0, -2.0, 0.0])
+    loss, grad = orc.l2_loss(np.zeros(0, np.float32), np.zeros(0, np.float32))
+    assert loss == 0.0 and grad.size == 0
