@@ -149,8 +149,12 @@ __device__ __forceinline__ void apply_map(const real *__restrict__ table, int k,
   }
 }
 
-// Copy the kernel-argument map table into LDS rows of type `real`.
-template <typename real, int DIM>
+__device__ inline void load_sincos_table();
+
+// Copy the kernel-argument map table into LDS rows of type `real`, the
+// selection thresholds and their guide; FP64 kernels (TRIG) also fill the
+// sine/cosine table of sincos_f64.
+template <typename real, int DIM, bool TRIG = (sizeof(real) == sizeof(double))>
 __device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
                                            uint32_t *th) {
   constexpr int S = RowStride<real, DIM>::value;
@@ -181,53 +185,54 @@ __device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
     }
     th[kMaxMaps + b] = lo | (hi << 16);
   }
+  if constexpr (TRIG) load_sincos_table();
 }
 
 // ---------------------------------------------------------------------------
 // Composed transforms on the copy q of p (p is never modified).
 // ---------------------------------------------------------------------------
-// FP64 sine and cosine for the transforms.  Arguments with |a| < 2^19 pi/2
-// are reduced by pi/2 after Cody and Waite (Software Manual for the
-// Elementary Functions, 1980): k = rint(2a/pi), r = a - k P1 - k P2 - k P3
-// with pi/2 = P1 + P2 + P3, P1 and P2 of 33 significant bits (so k P1, k P2
-// are exact for |k| <= 2^19).  sin r and cos r on [-pi/4, pi/4] are their
-// Taylor series to degree 13 and 14 (truncation below 3e-14 and 1e-15), and the
-// quadrant k mod 4 swaps and negates them.  Other arguments (large, infinite
-// or NaN) take the library's sincos in a function of its own, so that its
-// registers stay out of the calling loop; no lane of the workloads here
-// takes that path.
+// FP64 sine and cosine for the transforms, by table and angle addition.
+// k = rint(128 a / pi) and r = a - k pi/128 by Cody and Waite's reduction
+// (Software Manual for the Elementary Functions, 1980) with a three-part
+// constant whose first two parts have 33 significant bits (exact products
+// for |k| < 2^20), so |r| <= pi/256.  sin r and cos r are their Taylor series
+// to degree 5 and 6 (truncation below 1e-17), and
+//   sin a = S_j cos r + C_j sin r,  cos a = C_j cos r - S_j sin r,
+// with (S_j, C_j) = (sin, cos)(j pi/128), j = k mod 256, from a table in LDS
+// that every workgroup of an FP64 kernel fills once with the library routine
+// (load_table does it).  Arguments with |a| >= 25000, infinite or NaN take
+// the library's sincos in a function of its own (its registers stay out of
+// the calling loop); no lane of the workloads here does.
+constexpr int kSinCosTable = 256;
+__shared__ double2 s_sincos[kSinCosTable];
+
 __device__ __noinline__ void sincos_f64_wide(double a, double *sn, double *cs) { sincos(a, sn, cs); }
 
+__device__ inline void load_sincos_table() {
+  for (int i = threadIdx.x; i < kSinCosTable; i += blockDim.x) {
+    const double x = fma(static_cast<double>(i), 0x1.921fb54400000p-6,
+                         static_cast<double>(i) * 0x1.0b4611a600000p-40);
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    s_sincos[i] = make_double2(sn, cs);
+  }
+}
+
 __device__ __forceinline__ void sincos_f64(double a, double *sn, double *cs) {
-  if (!(fabs(a) < 823549.0)) {
+  if (!(fabs(a) < 25000.0)) {
     sincos_f64_wide(a, sn, cs);
     return;
   }
-  const double k = rint(a * 0.63661977236758134308);
-  double r = fma(-k, 0x1.921fb54400000p+0, a);
-  r = fma(-k, 0x1.0b4611a600000p-34, r);
-  r = fma(-k, 0x1.3198a2e037073p-69, r);
-  const double x2 = r * r;
-  double ps = 1.0 / 6227020800.0;
-  ps = fma(ps, x2, -1.0 / 39916800.0);
-  ps = fma(ps, x2, 1.0 / 362880.0);
-  ps = fma(ps, x2, -1.0 / 5040.0);
-  ps = fma(ps, x2, 1.0 / 120.0);
-  ps = fma(ps, x2, -1.0 / 6.0);
-  const double sr = fma(r * x2, ps, r);
-  double pc = -1.0 / 87178291200.0;
-  pc = fma(pc, x2, 1.0 / 479001600.0);
-  pc = fma(pc, x2, -1.0 / 3628800.0);
-  pc = fma(pc, x2, 1.0 / 40320.0);
-  pc = fma(pc, x2, -1.0 / 720.0);
-  pc = fma(pc, x2, 1.0 / 24.0);
-  pc = fma(pc, x2, -0.5);
-  const double cr = fma(pc, x2, 1.0);
-  const int q = static_cast<int>(k);
-  const double s0 = (q & 1) ? cr : sr;
-  const double c0 = (q & 1) ? sr : cr;
-  *sn = (q & 2) ? -s0 : s0;
-  *cs = ((q + 1) & 2) ? -c0 : c0;
+  const double k = rint(a * 40.743665431525205956834243423364);
+  double r = fma(-k, 0x1.921fb54400000p-6, a);
+  r = fma(-k, 0x1.0b4611a600000p-40, r);
+  r = fma(-k, 0x1.3198a2e037073p-75, r);
+  const double2 t = s_sincos[static_cast<int>(k) & (kSinCosTable - 1)];
+  const double z = r * r;
+  const double sr = fma(r * z, fma(z, 1.0 / 120.0, -1.0 / 6.0), r);
+  const double cr = fma(z, fma(z, fma(z, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  *sn = fma(t.x, cr, t.y * sr);
+  *cs = fma(t.y, cr, -(t.x * sr));
 }
 
 // FP64 square root for the transforms (a radius that feeds an angle or a

@@ -45,8 +45,13 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_emit(const InstDesc *__rest
     if (it >= n_items) break;
     const EmitItem item = items[it];
     const InstDesc &d = desc[item.inst];
-    load_table<real, 2>(d.mt, table, th);
+    load_table<real, 2, false>(d.mt, table, th);
     __syncthreads();
+    // the item's descriptor fields as values (uniform, so they stay in
+    // scalar registers instead of being reloaded inside the point loop)
+    const Window win = d.win;
+    const RunArgs ra = d.ra;
+    const int n_maps = d.mt.n_maps, n_search = d.mt.n_search, flags = d.mt.flags;
     BinArgs ba;
     ba.records = records + d.rec_base;
     ba.chunk_start = ctables + d.table_base;
@@ -58,9 +63,8 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_emit(const InstDesc *__rest
     Outputs out{nullptr, nullptr, nullptr, d.dropped};
     for (uint32_t b = 0; b < item.n_blocks; ++b)
       chaos_binned_block<real, 2, kFinalIdentity, kSelRuntime, false>(
-          table, th, d.mt.n_maps, d.mt.n_search, d.mt.flags, d.win, d.ra, nullptr,
-          ba, out,
-          item.first_block + b, stage, cnt, wsum);
+          table, th, n_maps, n_search, flags, win, ra, nullptr, ba, out, item.first_block + b,
+          stage, cnt, wsum);
     __syncthreads();
   }
 }
@@ -107,14 +111,17 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_direct(const InstDesc *__re
     if (it >= n_items) break;
     const EmitItem item = items[it];
     const InstDesc &d = desc[item.inst];
-    load_table<real, 2>(d.mt, table, th);
+    load_table<real, 2, false>(d.mt, table, th);
     __syncthreads();
+    const Window win = d.win;
+    const RunArgs ra = d.ra;
+    const int n_maps = d.mt.n_maps, n_search = d.mt.n_search, flags = d.mt.flags;
+    uint32_t *img = d.img;
     Outputs out{nullptr, nullptr, nullptr, d.dropped};
     for (uint32_t b = 0; b < item.n_blocks; ++b)
       chaos_direct_point<real, 2, kFinalIdentity, kSelRuntime, false, false>(
-          table, th, d.mt.n_maps, d.mt.n_search, d.mt.flags, d.win, d.ra, nullptr,
-          d.img,
-          nullptr, 0.0f, out, (item.first_block + b) * kBinBlock + threadIdx.x);
+          table, th, n_maps, n_search, flags, win, ra, nullptr, img, nullptr, 0.0f, out,
+          (item.first_block + b) * kBinBlock + threadIdx.x);
     __syncthreads();
   }
 }
