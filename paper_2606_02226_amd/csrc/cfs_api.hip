@@ -277,7 +277,7 @@ size_t binned_workspace(const cfs_run *run, const cfs_image *img, uint32_t per_i
   const bool depth = img->kind == CFS_IMAGE_U64_DEPTH;
   const BinPlan bp = bin_plan(binned_slice(run, depth, per_iter), run->n_iters, run->burn_in,
                               elems, depth, per_iter);
-  return align_up(bp.records_bytes) + 2 * align_up(bp.table_bytes);
+  return align_up(bp.records_bytes) + 2 * align_up(bp.table_bytes) + align_up(bp.sums_bytes);
 }
 
 // Point the binned arguments of one slice into the workspace.
@@ -287,6 +287,10 @@ void bind_workspace(BinArgs *ba, const BinPlan &bp, void *workspace) {
   char *tables = static_cast<char *>(workspace) + align_up(bp.records_bytes);
   ba->chunk_start = reinterpret_cast<uint32_t *>(tables);
   ba->tile_start = reinterpret_cast<uint32_t *>(tables + align_up(bp.table_bytes));
+  ba->tile_sums = bp.sums_bytes
+                      ? reinterpret_cast<uint32_t *>(tables + 2 * align_up(bp.table_bytes))
+                      : nullptr;
+  ba->n_rb = bp.n_rb;
   ba->n_chunks = bp.n_chunks;
   ba->flushes = bp.flushes;
   ba->n_tiles = bp.n_tiles;

@@ -154,9 +154,11 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
     for (uint32_t blk = 0; blk < bp.blocks; blk += p.blocks_per_item)
       emit.push_back(EmitItem{static_cast<uint32_t>(i), blk,
                               std::min<uint32_t>(p.blocks_per_item, bp.blocks - blk)});
-    d.log2g = bp.log2g;
+    // the batched accumulate walks every tile, so it aims at fewer workgroups
+    uint32_t parts = 1;
+    acc_shape(static_cast<uint64_t>(it.run.n_points) * (it.run.n_iters - it.run.burn_in),
+              bp.n_chunks, bp.n_tiles, kAccTargetGroups, &parts, &d.log2g);
     if (d.n_chunks) {
-      const uint32_t parts = bp.parts;
       for (uint32_t t = 0; t < d.n_tiles; ++t)
         for (uint32_t q = 0; q < parts; ++q)
           acc.push_back(AccItem{static_cast<uint32_t>(i), t,

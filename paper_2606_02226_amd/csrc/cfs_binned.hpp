@@ -404,10 +404,14 @@ __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
 }
 
 // [rows][cols] -> [cols][rows] through 64x64 LDS tiles (one workgroup of
-// 256 threads per tile).
+// 256 threads per tile).  With `sums`, also the sum (mod 2^32) of each
+// column over the tile's 64 rows, at sums[col * n_rb + by] (n_rb = row
+// blocks): for a run-start table, tile t's record total over the chunks of
+// row block by is sums[(t+1) n_rb + by] - sums[t n_rb + by].
 __device__ inline void transpose_tile(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                       uint32_t rows, uint32_t cols, uint32_t bx, uint32_t by,
-                                      uint32_t (*buf)[65]) {
+                                      uint32_t (*buf)[65], uint32_t *__restrict__ sums = nullptr,
+                                      uint32_t n_rb = 0) {
   const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (uint32_t r = ty; r < 64; r += 4) {
     const uint32_t gr = by * 64 + r, gc = bx * 64 + tx;
@@ -417,6 +421,12 @@ __device__ inline void transpose_tile(const uint32_t *__restrict__ in, uint32_t 
   for (uint32_t r = ty; r < 64; r += 4) {
     const uint32_t gc = bx * 64 + r, gr = by * 64 + tx;
     if (gc < cols && gr < rows) out[static_cast<size_t>(gc) * rows + gr] = buf[tx][r];
+  }
+  if (sums && ty == 0) {
+    uint32_t acc = 0;  // rows past the end were loaded as zero
+    for (int r = 0; r < 64; ++r) acc += buf[r][tx];
+    const uint32_t gc = bx * 64 + tx;
+    if (gc < cols) sums[static_cast<size_t>(gc) * n_rb + by] = acc;
   }
   __syncthreads();
 }

@@ -34,13 +34,15 @@ struct ChaosJob {
 
 // Records and table sizes of the binned splat for one launch of `points`.
 struct BinPlan {
-  uint32_t blocks, flushes, n_chunks, n_tiles, elems, parts, log2g;
-  size_t records_bytes, table_bytes;
+  uint32_t blocks, flushes, n_chunks, n_tiles, elems, parts, log2g, n_rb;
+  size_t records_bytes, table_bytes, sums_bytes;
 };
 // Accumulate launch shape for `records` count records in n_chunks chunks over
-// n_tiles tiles: workgroups per tile and lanes per run (2^log2g).
-void acc_shape(uint64_t records, uint32_t n_chunks, uint32_t n_tiles, uint32_t *parts,
-               uint32_t *log2g);
+// n_tiles tiles, aiming at `target` workgroups: workgroups per tile and lanes
+// per run (2^log2g).  bin_plan aims at kAccTargetSkip (its accumulate skips
+// tiles without records).
+void acc_shape(uint64_t records, uint32_t n_chunks, uint32_t n_tiles, uint32_t target,
+               uint32_t *parts, uint32_t *log2g);
 // per_iter: records a lane stages per step after burn-in (objects of a scene).
 BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t elems,
                  bool depth = false, uint32_t per_iter = 1);
@@ -70,8 +72,9 @@ struct SceneJob {
   BinArgs ba;
 };
 hipError_t launch_scene(const SceneJob &job, hipStream_t stream);
+// With `sums`: also the column sums of each 64-row block, [cols][ceil(rows / 64)].
 hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,
-                            hipStream_t stream);
+                            hipStream_t stream, uint32_t *sums = nullptr);
 
 struct GaussJob {
   bool equal;

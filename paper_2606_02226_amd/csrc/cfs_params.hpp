@@ -66,7 +66,7 @@ constexpr uint32_t kChunkCap = static_cast<uint32_t>(kBinBlock) * kBinSlots;
 constexpr int kTileBits = 14;
 constexpr uint32_t kTileElems = 1u << kTileBits;
 constexpr int kMaxTiles = 2048;  // images of up to 2^25 elements
-constexpr int kAccBlock = 512;
+constexpr int kAccBlock = 1024;  // two per CU: 8 waves per SIMD
 
 // Binned depth splat: records are (pixel | index << 24, FP32 depth bits),
 // kDSlots per lane per chunk, sorted by tiles of kDTileElems pixels whose
@@ -79,12 +79,29 @@ constexpr int kDAccBlock = 512;
 
 // The count accumulate aims at this many workgroups (two per CU of MI355X).
 constexpr uint32_t kAccTargetGroups = 512;
+// ... and at four times as many when it knows the tiles' record totals:
+// tiles without records then end at once, so the workgroups that do work
+// still fill the chip when much of the image is empty.
+constexpr uint32_t kAccTargetSkip = 4 * kAccTargetGroups;
+
+// Lanes per run of the count accumulate, 2^log2g: the smallest group whose
+// one pass of 4 records per lane covers a run of the mean length that starts
+// just above a 4-record boundary (longer runs take further passes; larger
+// groups measured slower).
+__host__ __device__ inline uint32_t run_lanes_log2(uint64_t mean_run) {
+  const uint64_t need = mean_run + 3u;
+  uint32_t lg = 0;
+  while (lg < 6 && (4ull << lg) < need) ++lg;
+  return lg;
+}
 
 struct BinArgs {
   uint16_t *records;     // [n_chunks][kChunkCap] in-tile offsets, runs by tile
   uint2 *drecords;       // depth images: [n_chunks][kDCap] (offset | index << 13, depth)
   uint32_t *chunk_start; // [n_chunks][n_tiles + 1]: run starts as the chunks write them
   uint32_t *tile_start;  // [n_tiles + 1][n_chunks]: the same, transposed for the accumulate
+  uint32_t *tile_sums;   // [n_tiles + 1][n_rb]: column sums of 64-chunk blocks (record totals)
+  uint32_t n_rb;         // 64-chunk blocks: ceil(n_chunks / 64)
   uint32_t n_chunks;     // chunks of this launch (= blocks * flushes)
   uint32_t flushes;      // chunks per workgroup
   uint32_t n_tiles;

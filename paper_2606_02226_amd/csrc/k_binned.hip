@@ -64,16 +64,44 @@ __global__ __launch_bounds__(kDAccBlock) void k_depth_accumulate(const uint2 *__
                         xcd_item(blockIdx.x, gridDim.x), keys, counts);
 }
 
+// Record total of tile t over all chunks, from the transpose's column sums
+// of 64-chunk blocks (every thread of the workgroup calls it and gets it).
+__device__ inline uint32_t tile_total(const uint32_t *__restrict__ sums, uint32_t n_rb, uint32_t t,
+                                      uint32_t *red) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t *lo = sums + static_cast<size_t>(t) * n_rb, *hi = lo + n_rb;
+  uint32_t s = 0;
+  for (uint32_t b = tid; b < n_rb; b += kAccBlock) s += hi[b] - lo[b];
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  uint32_t total = 0;
+#pragma unroll
+  for (int w = 0; w < kAccBlock / 64; ++w) total += red[w];
+  return total;
+}
+
 // One workgroup per (image tile, chunk range); the parts of a tile are
-// neighbours in the XCD-contiguous order.
+// neighbours in the XCD-contiguous order.  With the tiles' record totals
+// (`sums`), a tile without records is skipped and each tile walks its runs
+// with the lane group that its own mean run length asks for; without them,
+// every tile uses `log2g`.
 __global__ __launch_bounds__(kAccBlock) void k_tile_accumulate(const uint16_t *__restrict__ rec,
                                                                const uint32_t *__restrict__ tile_start,
-                                                               uint32_t n_chunks, uint32_t elems,
+                                                               const uint32_t *__restrict__ sums,
+                                                               uint32_t n_rb, uint32_t n_chunks,
+                                                               uint32_t elems,
                                                                uint32_t *__restrict__ img,
                                                                uint32_t parts, uint32_t log2g) {
   __shared__ uint32_t tile[kTileElems];
+  __shared__ uint32_t red[kAccBlock / 64];
   const uint32_t item = xcd_item(blockIdx.x, gridDim.x);
   const uint32_t t = item / parts, part = item % parts;
+  if (sums) {
+    const uint32_t total = tile_total(sums, n_rb, t, red);
+    if (total == 0) return;  // the same value in every lane
+    log2g = run_lanes_log2(total / n_chunks);
+  }
   const uint32_t c_lo = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * part / parts);
   const uint32_t c_hi = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * (part + 1) / parts);
   tile_accumulate(rec, tile_start, n_chunks, c_lo, c_hi, elems, img, t, log2g, tile);
@@ -81,30 +109,30 @@ __global__ __launch_bounds__(kAccBlock) void k_tile_accumulate(const uint16_t *_
 
 __global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ in,
                                                     uint32_t *__restrict__ out, uint32_t rows,
-                                                    uint32_t cols) {
+                                                    uint32_t cols, uint32_t *__restrict__ sums) {
   __shared__ uint32_t buf[64][65];
-  transpose_tile(in, out, rows, cols, blockIdx.x, blockIdx.y, buf);
+  transpose_tile(in, out, rows, cols, blockIdx.x, blockIdx.y, buf, sums, gridDim.y);
 }
 
 hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,
-                            hipStream_t s) {
+                            hipStream_t s, uint32_t *sums) {
   if (rows == 0 || cols == 0) return hipSuccess;
   hipLaunchKernelGGL(k_transpose, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, s, in, out,
-                     rows, cols);
+                     rows, cols, sums);
   return hipGetLastError();
 }
 
-void acc_shape(uint64_t records, uint32_t n_chunks, uint32_t n_tiles, uint32_t *parts,
-               uint32_t *log2g) {
+void acc_shape(uint64_t records, uint32_t n_chunks, uint32_t n_tiles, uint32_t target,
+               uint32_t *parts, uint32_t *log2g) {
   // mean run length -> lanes per run (a lane loads 4 records)
   const uint64_t runs = static_cast<uint64_t>(n_chunks) * (n_tiles ? n_tiles : 1);
   const uint64_t mean = runs ? records / runs : 0;
   uint32_t lg = 0;
   while (lg < 6 && (4ull << lg) < mean) ++lg;
   *log2g = lg;
-  // enough workgroups for two per CU, but at least one pass of groups each
+  // about `target` workgroups, but at least one pass of groups each
   const uint32_t groups = kAccBlock >> lg;
-  uint32_t p = n_tiles ? (kAccTargetGroups + n_tiles - 1) / n_tiles : 1;
+  uint32_t p = n_tiles ? (target + n_tiles - 1) / n_tiles : 1;
   const uint32_t pmax = n_chunks / groups > 1 ? n_chunks / groups : 1;
   *parts = p < 1 ? 1 : (p > pmax ? pmax : p);
 }
@@ -119,20 +147,24 @@ BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t e
   bp.n_tiles = depth ? (elems + kDTileElems - 1) / kDTileElems : (elems + kTileElems - 1) / kTileElems;
   bp.elems = elems;
   acc_shape(static_cast<uint64_t>(points) * (n_iters - burn_in) * per_iter, bp.n_chunks, bp.n_tiles,
-            &bp.parts, &bp.log2g);
+            kAccTargetSkip, &bp.parts, &bp.log2g);
   bp.records_bytes = depth ? static_cast<size_t>(bp.n_chunks) * kDCap * sizeof(uint2)
                            : static_cast<size_t>(bp.n_chunks) * kChunkCap * sizeof(uint16_t);
   bp.table_bytes = static_cast<size_t>(bp.n_tiles + 1) * bp.n_chunks * sizeof(uint32_t);  // each of two
+  bp.n_rb = (bp.n_chunks + 63) / 64;
+  bp.sums_bytes = depth ? 0 : static_cast<size_t>(bp.n_tiles + 1) * bp.n_rb * sizeof(uint32_t);
   return bp;
 }
 
 hipError_t launch_count_accumulate(const BinArgs &ba, uint32_t *img, hipStream_t s,
                                    const hipEvent_t *ev) {
-  hipError_t e = launch_transpose(ba.chunk_start, ba.tile_start, ba.n_chunks, ba.n_tiles + 1, s);
+  hipError_t e = launch_transpose(ba.chunk_start, ba.tile_start, ba.n_chunks, ba.n_tiles + 1, s,
+                                  ba.tile_sums);
   if (e != hipSuccess) return e;
   mark_phase(ev, 2, s);
   hipLaunchKernelGGL(k_tile_accumulate, dim3(ba.n_tiles * ba.parts), dim3(kAccBlock), 0, s,
-                     ba.records, ba.tile_start, ba.n_chunks, ba.elems, img, ba.parts, ba.log2g);
+                     ba.records, ba.tile_start, ba.tile_sums, ba.n_rb, ba.n_chunks, ba.elems, img,
+                     ba.parts, ba.log2g);
   e = hipGetLastError();
   mark_phase(ev, 3, s);
   return e;

@@ -278,6 +278,20 @@ def test_binned_drops_and_ragged(api, orc):
     assert got["dropped"] == ref["dropped"] > 0
 
 
+def test_binned_concentrated_and_empty_tiles(api):
+    # the attractor covers 64x64 pixels of a 4096x4096 image: 16 of 1024 tiles
+    # hold every record (runs of ~770 records: several passes of the widest
+    # lane group), the rest are skipped by their record totals
+    w = W.sierpinski(n_points=(1 << 16) + 3)
+    image = {"kind": "u32_count", "width": 4096, "height": 4096, "channels": 1,
+             "lo": [0, 0], "hi": [64, 64]}
+    a = _image_of(api, w, "f32", "direct", image=image)
+    b = _image_of(api, w, "f32", "binned", image=image)
+    assert np.array_equal(a["image"], b["image"]) and a["dropped"] == b["dropped"]
+    assert int(b["image"].astype(np.int64).sum()) + b["dropped"] == ((1 << 16) + 3) * 48
+    assert not b["image"][0, 64:, :].any() and not b["image"][0, :, 64:].any()
+
+
 def test_binned_slices_long_runs(api):
     # 1000 splats per point: the run is split into several slices that share
     # the workspace; the image must equal the direct splat's
