@@ -292,6 +292,55 @@ def test_binned_concentrated_and_empty_tiles(api):
     assert not b["image"][0, 64:, :].any() and not b["image"][0, :, 64:].any()
 
 
+def test_binned_on_side_stream(api):
+    # two calls into one image on a stream of their own (2^22 + 517 points,
+    # workspace passed in and reused), read after only that stream is waited
+    # for: equal to twice the direct splat
+    w = W.cfs_square(n_points=(1 << 22) + 517, side=1024)
+    ref = _image_of(api, w, "f64", "direct")["image"].astype(np.int64)
+    side = torch.cuda.Stream()
+    img = api.Image(w["image"], device=_dev())
+    ws_bytes = api.chaos_workspace_bytes(w["system"], w["run"], img, "f64", "binned")
+    assert ws_bytes > 0
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=_dev())
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        img.clear(side)
+        for _ in range(2):
+            api.chaos_game(w["system"], w["run"], img, precision="f64", splat_path="binned",
+                           workspace=ws, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    got = img.data.cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(got, 2 * ref)
+
+
+def test_binned_call_in_graph(api):
+    # the binned call (clear, chaos kernel, transpose, accumulate) captured
+    # into a graph: every replay, with eager calls in between, equals the
+    # eager result
+    w = W.cfs_square(n_points=(1 << 22) + 3, side=512)
+    eager = _image_of(api, w, "f32", "binned")["image"]
+    img = api.Image(w["image"], device=_dev())
+    ws_bytes = api.chaos_workspace_bytes(w["system"], w["run"], img, "f32", "binned")
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=_dev())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(g, stream=cap):
+            img.clear(cap)
+            api.chaos_game(w["system"], w["run"], img, precision="f32", splat_path="binned",
+                           workspace=ws, stream=cap)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(img.to_numpy()["image"], eager)
+        other = _image_of(api, w, "f32", "binned")["image"]
+        assert np.array_equal(other, eager)
+
+
 def test_binned_slices_long_runs(api):
     # 1000 splats per point: the run is split into several slices that share
     # the workspace; the image must equal the direct splat's
