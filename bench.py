@@ -69,6 +69,20 @@ def measured_traffic(precision):
     return t.get("bytes_per_launch")
 
 
+def measured_valu(precision):
+    """VALU instruction counts of the chaos kernel from a rocprofv3 --pmc run
+    (profiles/valu_cfs_square_<precision>.json), or None when the sources
+    changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"valu_cfs_square_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        v = json.load(fh)
+    if v.get("source_digest") != source_digest():
+        return None
+    return v
+
+
 def _pmc_rows(directory, counter):
     """(kernel name, value) of every dispatch in a rocprofv3 --pmc CSV run."""
     import csv
@@ -82,6 +96,32 @@ def _pmc_rows(directory, counter):
     if not rows:
         raise SystemExit(f"no {counter} rows under {directory}")
     return rows
+
+
+def summarise_valu(directory, precision):
+    """Write profiles/valu_cfs_square_<precision>.json from a rocprofv3 --pmc
+    run of this benchmark with SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU and SQ_WAVES:
+    mean per chaos-kernel dispatch, and the VALU wave-instructions issued per
+    point-iteration (the guard against a kernel that is busy but bloated)."""
+    import workloads
+    w = workloads.cfs_square()
+    N, T = w["run"]["n_points"], w["run"]["n_iters"]
+    out = {"source_digest": source_digest(), "precision": precision, "kernel": "k_chaos_binned",
+           "counters": {}}
+    for counter in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVES"):
+        vals = [v for k, v in _pmc_rows(directory, counter) if "k_chaos_binned" in k]
+        if not vals:
+            raise SystemExit(f"no k_chaos_binned {counter} rows under {directory}")
+        out["counters"][counter] = float(np.mean(vals))
+    wave_pt_its = N * T / 64.0
+    out["valu_insts_per_point_iteration"] = out["counters"]["SQ_INSTS_VALU"] / wave_pt_its
+    out["command"] = ("rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVES --output-format csv "
+                      "-d DIR -- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline "
+                      f"--no-forms --precision {precision}")
+    path = os.path.join(ROOT, "profiles", f"valu_cfs_square_{precision}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def summarise_pmc(fetch_dir, write_dir, precision):
@@ -125,6 +165,51 @@ def cpu_baseline(w, n_sample):
             "cores": 1, "kind": "oracle",
             "sample": f"{n_sample} of {w['run']['n_points']} points (all iterations, "
                       f"full image), single-threaded FP64, {dt:.1f} s"}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_all_cores(w, max_threads=16):
+    """The oracle on every host core: threads take equal point ranges of the
+    whole workload (the random streams are keyed by point id, so the range
+    images sum to the full image exactly); ctypes releases the GIL around the
+    oracle call."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = max(1, min(cores, max_threads))
+    n = w["run"]["n_points"]
+    bounds = [n * i // threads for i in range(threads + 1)]
+
+    def part(i):
+        run = dict(w["run"], n_points=bounds[i + 1] - bounds[i], point_offset=bounds[i])
+        return oracle.chaos_count(w["system"], run, w["image"])["image"]
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        images = list(ex.map(part, range(threads)))
+    dt = time.perf_counter() - t0
+    total = images[0].astype(np.uint64)
+    for im in images[1:]:
+        total += im
+    return {"value": n * w["run"]["n_iters"] / dt, "unit": "point-iterations/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"the whole workload ({n} points), {threads} threads over equal point "
+                      f"ranges, FP64, {dt:.1f} s, CPU: {_cpu_model()}",
+            "splats": int(total.sum())}
 
 
 def _timed(fn, reps, stream):
@@ -249,9 +334,16 @@ def main():
     ap.add_argument("--summarise-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_cfs_square_<precision>.json from two "
                          "rocprofv3 --pmc output folders and exit (no GPU needed)")
+    ap.add_argument("--summarise-valu", metavar="VALU_DIR",
+                    help="write profiles/valu_cfs_square_<precision>.json from a rocprofv3 "
+                         "--pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVES output folder and "
+                         "exit (no GPU needed)")
     args = ap.parse_args()
-    if args.summarise_pmc:
-        summarise_pmc(*args.summarise_pmc, args.precision)
+    if args.summarise_pmc or args.summarise_valu:
+        if args.summarise_pmc:
+            summarise_pmc(*args.summarise_pmc, args.precision)
+        if args.summarise_valu:
+            summarise_valu(args.summarise_valu, args.precision)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
@@ -346,10 +438,20 @@ def main():
                      "timing": "HIP events recorded by the library around the chaos kernel "
                                "on its stream (cfs_timing_enable), mean over the timed steps"},
     }
+    valu = measured_valu(args.precision)
+    if valu is not None and chaos_ms > 0:
+        # a wave64 VALU instruction occupies its SIMD for 4 cycles: the share of
+        # the kernel's SIMD cycles (1024 SIMDs at 2.4 GHz) that issue takes
+        issue = valu["counters"]["SQ_INSTS_VALU"] * 4.0 / (1024 * 2.4e9 * chaos_ms * 1e-3)
+        result["roofline"]["valu_counters"] = {
+            "insts_per_point_iteration": valu["valu_insts_per_point_iteration"],
+            "issue_share": issue,
+            "source": f"profiles/valu_cfs_square_{args.precision}.json"}
     if not args.no_forms:
         result["forms"] = forms(dev, args.precision)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, 1 << args.cpu_sample_log2)
+        result["cpu_baseline_all_cores"] = cpu_baseline_all_cores(w)
     print(json.dumps(result))
 
 
