@@ -341,6 +341,40 @@ def test_binned_call_in_graph(api):
         assert np.array_equal(other, eager)
 
 
+@pytest.mark.parametrize("px", [257, 258])
+def test_binned_single_pixel(api, px):
+    # one map x -> b sends every splat to pixel (px, 100): a single run per
+    # chunk in a single tile, one pixel counting n * 48 (several accumulate
+    # workgroups over chunk ranges, merged with device atomics); the image
+    # equals the direct splat's
+    n = (1 << 16) + 3
+    b = [[(px + 0.5) / 512.0, 100.5 / 512.0]]
+    system = W._system(np.zeros((1, 2, 2)), b)
+    run = W._run(n, 64, 16)
+    image = W._image("u32_count", 512, 512, 1, (0, 0), (1, 1))
+    w = {"system": system, "run": run, "image": image}
+    a = _image_of(api, w, "f32", "direct")
+    got = _image_of(api, w, "f32", "binned")
+    assert np.array_equal(a["image"], got["image"])
+    assert int(got["image"][0, 100, px]) == n * 48
+    assert int(got["image"].astype(np.int64).sum()) == n * 48
+
+
+def test_binned_two_pixels_with_large_counts(api):
+    # two maps x -> b0, b1 with probabilities 0.9 / 0.1 in a 4x4 image: one
+    # tile, counts above 2^16 per pixel, compared with the oracle
+    import oracle as orc
+    n = 40000
+    system = W._system(np.zeros((2, 2, 2)), [[0.25, 0.25], [0.75, 0.75]], prob=[0.9, 0.1])
+    run = W._run(n, 40, 8)
+    image = W._image("u32_count", 4, 4, 1, (0, 0), (1, 1))
+    w = {"system": system, "run": run, "image": image}
+    got = _image_of(api, w, "f64", "binned")
+    ref = orc.chaos_count(system, run, image)
+    assert np.array_equal(got["image"], ref["image"])
+    assert int(got["image"].max()) > 65535
+
+
 def test_binned_slices_long_runs(api):
     # 1000 splats per point: the run is split into several slices that share
     # the workspace; the image must equal the direct splat's
