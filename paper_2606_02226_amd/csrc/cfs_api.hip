@@ -285,8 +285,8 @@ void bind_workspace(BinArgs *ba, const BinPlan &bp, void *workspace) {
   ba->records = static_cast<uint16_t *>(workspace);
   ba->drecords = static_cast<uint2 *>(workspace);
   char *tables = static_cast<char *>(workspace) + align_up(bp.records_bytes);
-  ba->chunk_start = reinterpret_cast<uint32_t *>(tables);
-  ba->tile_start = reinterpret_cast<uint32_t *>(tables + align_up(bp.table_bytes));
+  ba->chunk_start = reinterpret_cast<uint16_t *>(tables);
+  ba->tile_start = reinterpret_cast<uint16_t *>(tables + align_up(bp.table_bytes));
   ba->tile_sums = bp.sums_bytes
                       ? reinterpret_cast<uint32_t *>(tables + 2 * align_up(bp.table_bytes))
                       : nullptr;

@@ -21,10 +21,10 @@ struct cfs_batch {
   EmitItem *d_items = nullptr;
   AccItem *d_acc = nullptr;
   TransItem *d_trans = nullptr;
-  uint32_t *d_ctables = nullptr;
+  uint16_t *d_ctables = nullptr;
   uint32_t *d_queues = nullptr;
   uint16_t *d_records = nullptr;
-  uint32_t *d_tables = nullptr;
+  uint16_t *d_tables = nullptr;
   uint32_t n_items32 = 0, n_items64 = 0, n_acc = 0, n_trans = 0;
   std::vector<int32_t> n_maps;
   hipStream_t capture_stream = nullptr;
@@ -202,9 +202,9 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
   if (p.splat_path == CFS_SPLAT_BINNED) {
     HIP_TRY(hipMalloc(&b->d_records, std::max<uint64_t>(rec_total, 1) * sizeof(uint16_t)),
             "hipMalloc(records)");
-    HIP_TRY(hipMalloc(&b->d_tables, std::max<uint64_t>(table_total, 1) * sizeof(uint32_t)),
+    HIP_TRY(hipMalloc(&b->d_tables, std::max<uint64_t>(table_total, 1) * sizeof(uint16_t)),
             "hipMalloc(tables)");
-    HIP_TRY(hipMalloc(&b->d_ctables, std::max<uint64_t>(table_total, 1) * sizeof(uint32_t)),
+    HIP_TRY(hipMalloc(&b->d_ctables, std::max<uint64_t>(table_total, 1) * sizeof(uint16_t)),
             "hipMalloc(chunk tables)");
     HIP_TRY(hipMalloc(&b->d_trans, sizeof(TransItem) * std::max<size_t>(trans.size(), 1)),
             "hipMalloc(transpose items)");

@@ -48,8 +48,8 @@ struct BatchLaunch {
   const TransItem *trans;
   uint32_t n_trans;
   uint16_t *records;
-  uint32_t *ctables;  // [chunk][tile + 1] per instance
-  uint32_t *tables;   // [tile + 1][chunk] per instance
+  uint16_t *ctables;  // [chunk][tile + 1] per instance: run starts within the chunk
+  uint16_t *tables;   // [tile + 1][chunk] per instance
   uint32_t emit_grid, acc_grid;
   bool direct;
 };

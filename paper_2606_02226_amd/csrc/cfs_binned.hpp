@@ -67,8 +67,10 @@ __device__ inline void flush_chunk(uint32_t *stage, uint32_t *cnt, uint32_t *wsu
   const int tid = threadIdx.x;
   const uint32_t total = block_exclusive_scan(cnt, ba.n_tiles, wsum);
   const uint32_t base = chunk * kChunkCap;
-  uint32_t *row = ba.chunk_start + static_cast<size_t>(chunk) * (ba.n_tiles + 1);
-  for (uint32_t t = tid; t <= ba.n_tiles; t += kBinBlock) row[t] = base + (t < ba.n_tiles ? cnt[t] : total);
+  // run starts relative to the chunk (at most kChunkCap: 16 bits)
+  uint16_t *row = ba.chunk_start + static_cast<size_t>(chunk) * (ba.n_tiles + 1);
+  for (uint32_t t = tid; t <= ba.n_tiles; t += kBinBlock)
+    row[t] = static_cast<uint16_t>(t < ba.n_tiles ? cnt[t] : total);
   uint32_t e[kBinSlots];
 #pragma unroll
   for (int i = 0; i < kBinSlots; ++i) e[i] = i < used_slots ? stage[i * kBinBlock + tid] : kInvalid;
@@ -190,8 +192,9 @@ __device__ inline void flush_depth_chunk(uint2 *stage, uint32_t *cnt, uint32_t *
   const int tid = threadIdx.x;
   const uint32_t total = block_exclusive_scan(cnt, ba.n_tiles, wsum);
   const uint32_t base = chunk * kDCap;
-  uint32_t *row = ba.chunk_start + static_cast<size_t>(chunk) * (ba.n_tiles + 1);
-  for (uint32_t t = tid; t <= ba.n_tiles; t += kBinBlock) row[t] = base + (t < ba.n_tiles ? cnt[t] : total);
+  uint16_t *row = ba.chunk_start + static_cast<size_t>(chunk) * (ba.n_tiles + 1);
+  for (uint32_t t = tid; t <= ba.n_tiles; t += kBinBlock)
+    row[t] = static_cast<uint16_t>(t < ba.n_tiles ? cnt[t] : total);
   uint2 e[kDSlots];
 #pragma unroll
   for (int i = 0; i < kDSlots; ++i)
@@ -286,7 +289,7 @@ __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_m
 // counts of every chunk's records, then merged into the image (min) and the
 // density (sum).  Every thread calls it; keys/counts are kDTileElems each.
 __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
-                                             const uint32_t *__restrict__ tile_start,
+                                             const uint16_t *__restrict__ tile_start,
                                              uint32_t n_chunks, uint32_t elems,
                                              unsigned long long *__restrict__ img,
                                              uint32_t *__restrict__ density, uint32_t t,
@@ -297,10 +300,10 @@ __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
     counts[i] = 0u;
   }
   __syncthreads();
-  const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
-  const uint32_t *row1 = row0 + n_chunks;
+  const uint16_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
+  const uint16_t *row1 = row0 + n_chunks;
   for (uint32_t c = tid; c < n_chunks; c += kDAccBlock) {
-    const uint32_t s = row0[c], e = row1[c];
+    const uint32_t s = c * kDCap + row0[c], e = c * kDCap + row1[c];
     for (uint32_t i = s; i < e; i += 4u) {
       uint2 v[4];
 #pragma unroll
@@ -353,15 +356,15 @@ __device__ inline void count_records(uint32_t *tile, uint2 v, uint32_t at, uint3
 }
 
 __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
-                                       const uint32_t *__restrict__ tile_start, uint32_t n_chunks,
+                                       const uint16_t *__restrict__ tile_start, uint32_t n_chunks,
                                        uint32_t c_lo, uint32_t c_hi, uint32_t elems,
                                        uint32_t *__restrict__ img, uint32_t t, uint32_t log2g,
                                        uint32_t *tile) {
   const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < kTileElems; i += kAccBlock) tile[i] = 0u;
   __syncthreads();
-  const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
-  const uint32_t *row1 = row0 + n_chunks;
+  const uint16_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
+  const uint16_t *row1 = row0 + n_chunks;
   const uint32_t g = 1u << log2g, lane = tid & (g - 1u);
   const uint32_t groups = kAccBlock >> log2g;
   // kRunsInFlight runs per group at a time: their bounds, then the first
@@ -371,8 +374,15 @@ __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
 #pragma unroll
     for (int u = 0; u < kRunsInFlight; ++u) {
       const uint32_t c = c0 + u * groups;
-      s[u] = c < c_hi ? row0[c] : 0u;
-      e[u] = c < c_hi ? row1[c] : 0u;
+      s[u] = c < c_hi ? static_cast<uint32_t>(row0[c]) : 0u;
+      e[u] = c < c_hi ? static_cast<uint32_t>(row1[c]) : 0u;
+    }
+    // chunk bases (chunk indices and kChunkCap fit 24 bits: full-rate multiply)
+#pragma unroll
+    for (int u = 0; u < kRunsInFlight; ++u) {
+      const uint32_t base = __umul24(c0 + u * groups, kChunkCap);
+      s[u] += base;
+      e[u] += base;
     }
     uint2 v[kRunsInFlight];
 #pragma unroll
@@ -408,10 +418,10 @@ __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
 // column over the tile's 64 rows, at sums[col * n_rb + by] (n_rb = row
 // blocks): for a run-start table, tile t's record total over the chunks of
 // row block by is sums[(t+1) n_rb + by] - sums[t n_rb + by].
-__device__ inline void transpose_tile(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                                      uint32_t rows, uint32_t cols, uint32_t bx, uint32_t by,
-                                      uint32_t (*buf)[65], uint32_t *__restrict__ sums = nullptr,
-                                      uint32_t n_rb = 0) {
+template <typename T>
+__device__ inline void transpose_tile(const T *__restrict__ in, T *__restrict__ out, uint32_t rows,
+                                      uint32_t cols, uint32_t bx, uint32_t by, uint32_t (*buf)[65],
+                                      uint32_t *__restrict__ sums = nullptr, uint32_t n_rb = 0) {
   const uint32_t tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (uint32_t r = ty; r < 64; r += 4) {
     const uint32_t gr = by * 64 + r, gc = bx * 64 + tx;
@@ -420,7 +430,7 @@ __device__ inline void transpose_tile(const uint32_t *__restrict__ in, uint32_t 
   __syncthreads();
   for (uint32_t r = ty; r < 64; r += 4) {
     const uint32_t gc = bx * 64 + r, gr = by * 64 + tx;
-    if (gc < cols && gr < rows) out[static_cast<size_t>(gc) * rows + gr] = buf[tx][r];
+    if (gc < cols && gr < rows) out[static_cast<size_t>(gc) * rows + gr] = static_cast<T>(buf[tx][r]);
   }
   if (sums && ty == 0) {
     uint32_t acc = 0;  // rows past the end were loaded as zero

@@ -75,6 +75,8 @@ hipError_t launch_scene(const SceneJob &job, hipStream_t stream);
 // With `sums`: also the column sums of each 64-row block, [cols][ceil(rows / 64)].
 hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,
                             hipStream_t stream, uint32_t *sums = nullptr);
+hipError_t launch_transpose(const uint16_t *in, uint16_t *out, uint32_t rows, uint32_t cols,
+                            hipStream_t stream, uint32_t *sums = nullptr);
 
 struct GaussJob {
   bool equal;

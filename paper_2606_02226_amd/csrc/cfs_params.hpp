@@ -98,8 +98,8 @@ __host__ __device__ inline uint32_t run_lanes_log2(uint64_t mean_run) {
 struct BinArgs {
   uint16_t *records;     // [n_chunks][kChunkCap] in-tile offsets, runs by tile
   uint2 *drecords;       // depth images: [n_chunks][kDCap] (offset | index << 13, depth)
-  uint32_t *chunk_start; // [n_chunks][n_tiles + 1]: run starts as the chunks write them
-  uint32_t *tile_start;  // [n_tiles + 1][n_chunks]: the same, transposed for the accumulate
+  uint16_t *chunk_start; // [n_chunks][n_tiles + 1]: run starts within each chunk, as written
+  uint16_t *tile_start;  // [n_tiles + 1][n_chunks]: the same, transposed for the accumulate
   uint32_t *tile_sums;   // [n_tiles + 1][n_rb]: column sums of 64-chunk blocks (record totals)
   uint32_t n_rb;         // 64-chunk blocks: ceil(n_chunks / 64)
   uint32_t n_chunks;     // chunks of this launch (= blocks * flushes)

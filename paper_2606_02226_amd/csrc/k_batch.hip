@@ -30,8 +30,8 @@ template <typename real>
 __global__ __launch_bounds__(kBinBlock) void k_batch_emit(const InstDesc *__restrict__ desc,
                                                           const EmitItem *__restrict__ items,
                                                           uint32_t n_items, uint32_t *queue,
-                                                          uint16_t *records, uint32_t *ctables,
-                                                          uint32_t *tables) {
+                                                          uint16_t *records, uint16_t *ctables,
+                                                          uint16_t *tables) {
   __shared__ real table[kMaxMaps * RowStride<real, 2>::value];
   __shared__ uint32_t th[kThWords];
   __shared__ uint32_t stage[kChunkCap];
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kAccBlock) void k_batch_accumulate(const InstDesc *
                                                                 const AccItem *__restrict__ items,
                                                                 uint32_t n_items, uint32_t *queue,
                                                                 const uint16_t *records,
-                                                                const uint32_t *tables) {
+                                                                const uint16_t *tables) {
   __shared__ uint32_t tile[kTileElems];
   __shared__ uint32_t slot;
   for (;;) {
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kAccBlock) void k_batch_accumulate(const InstDesc *
 // (one 64x64 block per workgroup).
 __global__ __launch_bounds__(256) void k_batch_transpose(const InstDesc *__restrict__ desc,
                                                          const TransItem *__restrict__ items,
-                                                         const uint32_t *ctables, uint32_t *tables) {
+                                                         const uint16_t *ctables, uint16_t *tables) {
   __shared__ uint32_t buf[64][65];
   const TransItem it = items[blockIdx.x];
   const InstDesc &d = desc[it.inst];

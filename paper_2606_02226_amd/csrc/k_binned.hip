@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_depth_binned(MapTable<3> mt
 }
 
 __global__ __launch_bounds__(kDAccBlock) void k_depth_accumulate(const uint2 *__restrict__ rec,
-                                                                 const uint32_t *__restrict__ tile_start,
+                                                                 const uint16_t *__restrict__ tile_start,
                                                                  uint32_t n_chunks, uint32_t elems,
                                                                  unsigned long long *img,
                                                                  uint32_t *density) {
@@ -87,7 +87,7 @@ __device__ inline uint32_t tile_total(const uint32_t *__restrict__ sums, uint32_
 // with the lane group that its own mean run length asks for; without them,
 // every tile uses `log2g`.
 __global__ __launch_bounds__(kAccBlock) void k_tile_accumulate(const uint16_t *__restrict__ rec,
-                                                               const uint32_t *__restrict__ tile_start,
+                                                               const uint16_t *__restrict__ tile_start,
                                                                const uint32_t *__restrict__ sums,
                                                                uint32_t n_rb, uint32_t n_chunks,
                                                                uint32_t elems,
@@ -107,19 +107,31 @@ __global__ __launch_bounds__(kAccBlock) void k_tile_accumulate(const uint16_t *_
   tile_accumulate(rec, tile_start, n_chunks, c_lo, c_hi, elems, img, t, log2g, tile);
 }
 
-__global__ __launch_bounds__(256) void k_transpose(const uint32_t *__restrict__ in,
-                                                    uint32_t *__restrict__ out, uint32_t rows,
-                                                    uint32_t cols, uint32_t *__restrict__ sums) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T *__restrict__ in, T *__restrict__ out,
+                                                    uint32_t rows, uint32_t cols,
+                                                    uint32_t *__restrict__ sums) {
   __shared__ uint32_t buf[64][65];
   transpose_tile(in, out, rows, cols, blockIdx.x, blockIdx.y, buf, sums, gridDim.y);
 }
 
+template <typename T>
+static hipError_t launch_transpose_t(const T *in, T *out, uint32_t rows, uint32_t cols,
+                                     hipStream_t s, uint32_t *sums) {
+  if (rows == 0 || cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose<T>, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, s, in,
+                     out, rows, cols, sums);
+  return hipGetLastError();
+}
+
 hipError_t launch_transpose(const uint32_t *in, uint32_t *out, uint32_t rows, uint32_t cols,
                             hipStream_t s, uint32_t *sums) {
-  if (rows == 0 || cols == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_transpose, dim3((cols + 63) / 64, (rows + 63) / 64), dim3(256), 0, s, in, out,
-                     rows, cols, sums);
-  return hipGetLastError();
+  return launch_transpose_t(in, out, rows, cols, s, sums);
+}
+
+hipError_t launch_transpose(const uint16_t *in, uint16_t *out, uint32_t rows, uint32_t cols,
+                            hipStream_t s, uint32_t *sums) {
+  return launch_transpose_t(in, out, rows, cols, s, sums);
 }
 
 void acc_shape(uint64_t records, uint32_t n_chunks, uint32_t n_tiles, uint32_t target,
@@ -150,7 +162,7 @@ BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t e
             kAccTargetSkip, &bp.parts, &bp.log2g);
   bp.records_bytes = depth ? static_cast<size_t>(bp.n_chunks) * kDCap * sizeof(uint2)
                            : static_cast<size_t>(bp.n_chunks) * kChunkCap * sizeof(uint16_t);
-  bp.table_bytes = static_cast<size_t>(bp.n_tiles + 1) * bp.n_chunks * sizeof(uint32_t);  // each of two
+  bp.table_bytes = static_cast<size_t>(bp.n_tiles + 1) * bp.n_chunks * sizeof(uint16_t);  // each of two
   bp.n_rb = (bp.n_chunks + 63) / 64;
   bp.sums_bytes = depth ? 0 : static_cast<size_t>(bp.n_tiles + 1) * bp.n_rb * sizeof(uint32_t);
   return bp;
