@@ -337,3 +337,21 @@ def test_timing_hook_without_calls(L):
     assert lib.cfs_timing_read(buf, 2, C.byref(n)) == L.CFS_OK and n.value == 0
     assert lib.cfs_timing_enable(0) == L.CFS_OK
     assert lib.cfs_timing_read(None, 0, None) == L.CFS_E_INVALID
+
+
+def test_binned_image_size_limit(L):
+    # count images up to 2^25 elements take the binned splat; one more row
+    # is refused for BINNED (and AUTO falls back to the direct splat)
+    lib = L.load()
+    s, keep = _system(L)
+    r = L.CfsRun(0, 0, 1 << 20, 0, 8, 2, 0, 2)
+    ok = _image(L, W=8192, H=4096)
+    ok.data = C.c_void_p(256)  # never dereferenced: nothing is launched
+    assert lib.cfs_chaos_game_workspace(C.byref(s), C.byref(r), C.byref(ok)) > 0
+    big = _image(L, W=8192, H=4097)
+    big.data = C.c_void_p(256)  # never dereferenced: the call fails first
+    assert lib.cfs_chaos_game_workspace(C.byref(s), C.byref(r), C.byref(big)) == 0
+    rc = lib.cfs_chaos_game(C.byref(s), C.byref(r), C.byref(big), None, None, None, None, 0,
+                            None)
+    assert rc == L.CFS_E_UNSUPPORTED
+    assert "at most 33554432 elements" in lib.cfs_last_error().decode()

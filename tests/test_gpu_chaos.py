@@ -375,6 +375,18 @@ def test_binned_two_pixels_with_large_counts(api):
     assert int(got["image"].max()) > 65535
 
 
+def test_binned_largest_image(api):
+    # the largest count image the binned splat takes (2^25 elements: 2048
+    # tiles, the last one full) against the direct splat
+    w = W.sierpinski(n_points=(1 << 18) + 11)
+    image = {"kind": "u32_count", "width": 8192, "height": 4096, "channels": 1,
+             "lo": [0, 0], "hi": [1, 1]}
+    a = _image_of(api, w, "f32", "direct", image=image)
+    b = _image_of(api, w, "f32", "binned", image=image)
+    assert np.array_equal(a["image"], b["image"]) and a["dropped"] == b["dropped"]
+    assert int(b["image"].astype(np.int64).sum()) + b["dropped"] == ((1 << 18) + 11) * 48
+
+
 def test_binned_slices_long_runs(api):
     # 1000 splats per point: the run is split into several slices that share
     # the workspace; the image must equal the direct splat's
