@@ -16,8 +16,10 @@ Parity status:
                      composition order; circle maps: invariant uniform disk
                      (moments of r^2, half-disk per index)
   chaos_depth        pinned: Menger occupancy of the 3^k grid and box
-                     dimension for the 3D points; the projected depth image
-                     itself is parity unpinned beyond the oracle
+                     dimension for the 3D points; the splat coordinates by
+                     inverting the camera and the twist back to the points;
+                     the depth image and density by brute-force assembly
+                     from those splats and the steps' map indices
   splat_gauss        pinned: total mass closed form, separable kernel sums
   splat_gauss_backward pinned: central finite differences of splat_gauss,
                      zero gradient at the target

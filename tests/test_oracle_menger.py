@@ -91,3 +91,37 @@ def test_depth_keys(orc):
     rad = math.sqrt(3) / 2
     assert z.min() >= dist - rad - 1e-5 and z.max() <= dist + rad + 1e-5
     assert int(dens.sum()) + r["dropped"] == (1 << 14) * 16
+
+
+def test_depth_image_from_splats_brute_force(orc):
+    # the depth image assembled by brute force from the oracle's own splat
+    # coordinates and the map index of each step (drawn by the same random
+    # streams, so the count game of the untransformed system gives them):
+    # drop depth <= near and pixels outside the window, key = FP32 bits of
+    # the depth << 32 | index, minimum per pixel, density = splats per pixel
+    w = W.menger(n_points=3000, side=64)
+    run, image, near = w["run"], w["image"], w["image"]["near"]
+    r = orc.chaos_depth(w["system"], run, image, near, want_splats=True)
+    plain = dict(w["system"], final_kind="identity")
+    idx = orc.chaos_count(plain, run, {"kind": "u32_count", "width": 4, "height": 4,
+                                       "channels": 1, "lo": [0, 0], "hi": [1, 1]},
+                          want_indices=True)["indices"]
+    B = run["burn_in"]
+    s = r["splats"].reshape(-1, 3)
+    k = idx[:, B:].reshape(-1).astype(np.uint64)
+    H, Wd = image["height"], image["width"]
+    fin = np.isfinite(s).all(axis=1)
+    z = np.where(fin, s[:, 2], 0.0)
+    px = np.floor(np.where(fin, s[:, 0], -1.0)).astype(np.int64)
+    py = np.floor(np.where(fin, s[:, 1], -1.0)).astype(np.int64)
+    keep = fin & (z > near) & (px >= 0) & (px < Wd) & (py >= 0) & (py < H)
+    zb = np.float32(z[keep]).view(np.uint32).astype(np.uint64)
+    key = (zb << np.uint64(32)) | k[keep]
+    flat = py[keep] * Wd + px[keep]
+    depth = np.full(H * Wd, np.iinfo(np.uint64).max, np.uint64)
+    np.minimum.at(depth, flat, key)
+    dens = np.bincount(flat, minlength=H * Wd).astype(np.uint32)
+    assert np.array_equal(depth.reshape(H, Wd), r["depth"])
+    assert np.array_equal(dens.reshape(H, Wd), r["density"])
+    assert r["dropped"] == int((~keep).sum())
+    assert keep.mean() > 0.9
