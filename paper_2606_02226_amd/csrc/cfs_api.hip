@@ -334,6 +334,7 @@ SceneArgs pack_objects(const cfs_object *objects, int32_t n_objects) {
   SceneArgs sc;
   std::memset(&sc, 0, sizeof sc);
   sc.n_obj = n_objects;
+  uint32_t rows = 0;  // LDS placement rows handed out so far
   for (int o = 0; o < n_objects; ++o) {
     const cfs_object &ob = objects[o];
     SceneObject &d = sc.obj[o];
@@ -348,7 +349,14 @@ SceneArgs pack_objects(const cfs_object *objects, int32_t n_objects) {
     d.copy_span[1] = ob.copy_span[1];
     d.scale_lo = ob.scale_lo;
     d.scale_span = ob.scale_span;
-    if (ob.n_copies > 1) sc.any_copies = 1;
+    d.tab_base = -1;
+    if (ob.n_copies > 1) {
+      sc.any_copies = 1;
+      if (ob.n_copies <= kSceneCopyTable - rows) {
+        d.tab_base = static_cast<int32_t>(rows);
+        rows += ob.n_copies;
+      }
+    }
   }
   return sc;
 }

@@ -148,11 +148,16 @@ struct GaussCkpt {
 // Objects of a scene (several objects from one primitive): transform kind
 // and its first 8 parameters, placement, channel and duplication.
 constexpr int kMaxObjects = 8;
+// Copies of duplicated objects whose placements a scene workgroup keeps in
+// LDS (filled once per workgroup from the same random streams; objects past
+// this budget draw each copy's placement per splat).
+constexpr uint32_t kSceneCopyTable = 512;
+
 struct SceneObject {
   int32_t kind;
   int32_t channel;
   uint32_t n_copies;
-  int32_t pad;
+  int32_t tab_base;  // first LDS placement row of this object's copies, or -1
   float fp[8];
   float place[6];
   float copy_lo[2], copy_span[2];

@@ -18,12 +18,43 @@ namespace cfs {
 
 namespace {
 
+// Placement of copy c of object o: scale and offset from Philox block
+// (c, o, instance, 3).
+template <typename real>
+__device__ __forceinline__ void copy_placement(const SceneObject &ob, uint32_t c, uint32_t o,
+                                               uint32_t instance, uint32_t k0, uint32_t k1,
+                                               real *sc, real *off0, real *off1) {
+  const Block4 w = philox10(c, o, instance, 3u, k0, k1);
+  const real e0 = static_cast<real>(w.w0 >> 8) * static_cast<real>(0x1p-24);
+  const real e1 = static_cast<real>(w.w1 >> 8) * static_cast<real>(0x1p-24);
+  const real e2 = static_cast<real>(w.w2 >> 8) * static_cast<real>(0x1p-24);
+  *sc = static_cast<real>(ob.scale_lo) + static_cast<real>(ob.scale_span) * e2;
+  *off0 = static_cast<real>(ob.copy_lo[0]) + static_cast<real>(ob.copy_span[0]) * e0;
+  *off1 = static_cast<real>(ob.copy_lo[1]) + static_cast<real>(ob.copy_span[1]) * e1;
+}
+
+// Every workgroup fills the LDS placement rows of the objects that have them
+// (kSceneCopyTable rows of scale, offset x, offset y); callers sync after.
+template <typename real>
+__device__ inline void load_copy_table(const SceneArgs &sc, const RunArgs &ra, real *ctab) {
+  for (int o = 0; o < sc.n_obj; ++o) {
+    const SceneObject &ob = sc.obj[o];
+    if (ob.tab_base < 0) continue;
+    for (uint32_t c = threadIdx.x; c < ob.n_copies; c += blockDim.x) {
+      real *row = ctab + 3 * (static_cast<uint32_t>(ob.tab_base) + c);
+      copy_placement<real>(ob, c, static_cast<uint32_t>(o), ra.instance, ra.k0, ra.k1, row,
+                           row + 1, row + 2);
+    }
+  }
+}
+
 // The object transform (a wave-uniform branch on the kind), then placement
-// and duplication.  `cu` is the copy draw of this iteration.
+// and duplication.  `cu` is the copy draw of this iteration; the copy's
+// placement comes from the LDS rows when the object has them.
 template <typename real>
 __device__ __forceinline__ void object_copy(const SceneObject &ob, uint32_t o, const real p[2],
                                             uint32_t cu, uint32_t instance, uint32_t k0,
-                                            uint32_t k1, real q[2]) {
+                                            uint32_t k1, const real *ctab, real q[2]) {
   real g[2], dz;
   switch (ob.kind) {
     case kFinalSwirl: final_transform<real, kFinalSwirl, 2>(ob.fp, p, g, &dz); break;
@@ -37,13 +68,17 @@ __device__ __forceinline__ void object_copy(const SceneObject &ob, uint32_t o, c
          static_cast<real>(ob.place[5]);
   if (ob.n_copies > 1) {
     const uint32_t c = __umulhi((2u * o + 1u) * cu, ob.n_copies);
-    const Block4 w = philox10(c, o, instance, 3u, k0, k1);
-    const real e0 = static_cast<real>(w.w0 >> 8) * static_cast<real>(0x1p-24);
-    const real e1 = static_cast<real>(w.w1 >> 8) * static_cast<real>(0x1p-24);
-    const real e2 = static_cast<real>(w.w2 >> 8) * static_cast<real>(0x1p-24);
-    const real sc = static_cast<real>(ob.scale_lo) + static_cast<real>(ob.scale_span) * e2;
-    q[0] = sc * q[0] + (static_cast<real>(ob.copy_lo[0]) + static_cast<real>(ob.copy_span[0]) * e0);
-    q[1] = sc * q[1] + (static_cast<real>(ob.copy_lo[1]) + static_cast<real>(ob.copy_span[1]) * e1);
+    real sc, off0, off1;
+    if (ob.tab_base >= 0) {
+      const real *row = ctab + 3 * (static_cast<uint32_t>(ob.tab_base) + c);
+      sc = row[0];
+      off0 = row[1];
+      off1 = row[2];
+    } else {
+      copy_placement<real>(ob, c, o, instance, k0, k1, &sc, &off0, &off1);
+    }
+    q[0] = sc * q[0] + off0;
+    q[1] = sc * q[1] + off1;
   }
 }
 
@@ -55,7 +90,9 @@ __global__ __launch_bounds__(kSceneBlock) void k_scene(MapTable<2> mt, Window wi
                                                        unsigned long long *dropped_out) {
   __shared__ real table[kMaxMaps * RowStride<real, 2>::value];
   __shared__ uint32_t th[kThWords];
+  __shared__ real ctab[3 * kSceneCopyTable];
   load_table<real, 2>(mt, table, th);
+  load_copy_table<real>(sc, ra, ctab);
   __syncthreads();
   const uint32_t n = blockIdx.x * kSceneBlock + threadIdx.x;
   if (n >= ra.n_points) return;
@@ -79,7 +116,8 @@ __global__ __launch_bounds__(kSceneBlock) void k_scene(MapTable<2> mt, Window wi
       const uint32_t cu = word_of(cblk, j);
       for (int o = 0; o < sc.n_obj; ++o) {
         real q[2];
-        object_copy<real>(sc.obj[o], static_cast<uint32_t>(o), p, cu, ra.instance, ra.k0, ra.k1, q);
+        object_copy<real>(sc.obj[o], static_cast<uint32_t>(o), p, cu, ra.instance, ra.k0, ra.k1,
+                          ctab, q);
         int ix;
         const int pix = bin_pixel<real>(q, win, &ix);
         if (pix < 0) {
@@ -99,9 +137,12 @@ __global__ __launch_bounds__(kSceneBlock) void k_scene(MapTable<2> mt, Window wi
 
 // Binned: every lane stages n_obj records per step after burn-in; a full
 // stage of kBinSlots records per lane is flushed (the flush is block-wide,
-// and every lane reaches it after the same number of records).
+// and every lane reaches it after the same number of records).  Four waves
+// per SIMD (two workgroups per CU) are asked for: the FP64 object transforms
+// would otherwise take 160 VGPRs and leave one workgroup per CU (3.65 ms
+// instead of 4.28 ms per 1920x1080 frame, with a few spilled registers).
 template <typename real, int SEL>
-__global__ __launch_bounds__(kBinBlock) void k_scene_binned(MapTable<2> mt, Window win,
+__global__ __launch_bounds__(kBinBlock, 4) void k_scene_binned(MapTable<2> mt, Window win,
                                                             RunArgs ra, SceneArgs sc, BinArgs ba,
                                                             unsigned long long *dropped_out) {
   __shared__ real table[kMaxMaps * RowStride<real, 2>::value];
@@ -109,7 +150,9 @@ __global__ __launch_bounds__(kBinBlock) void k_scene_binned(MapTable<2> mt, Wind
   __shared__ uint32_t stage[kChunkCap];
   __shared__ uint32_t cnt[kMaxTiles];
   __shared__ uint32_t wsum[kWaves + 1];
+  __shared__ real ctab[3 * kSceneCopyTable];
   load_table<real, 2>(mt, table, th);
+  load_copy_table<real>(sc, ra, ctab);
   for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
   __syncthreads();
 
@@ -141,7 +184,7 @@ __global__ __launch_bounds__(kBinBlock) void k_scene_binned(MapTable<2> mt, Wind
         if (active) {
           real q[2];
           object_copy<real>(sc.obj[o], static_cast<uint32_t>(o), p, cu, ra.instance, ra.k0, ra.k1,
-                            q);
+                            ctab, q);
           int ix;
           const int pix = bin_pixel<real>(q, win, &ix);
           if (pix >= 0)

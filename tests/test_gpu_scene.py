@@ -126,3 +126,21 @@ def test_full_size_scene_splits_and_sample(api, orc):
     ref = orc.chaos_scene(w["system"], w["objects"], sample, w["image"])
     assert rel_l1(got["image"], ref["image"]) <= 1e-4
     assert got["dropped"] == ref["dropped"]
+
+
+def test_scene_copy_tables_and_streamed_copies(api, orc):
+    # three duplicated objects whose copies overflow the workgroup's table
+    # of copy placements: the first (300 copies) and the third (200) get
+    # table rows, the second (300) no longer fits and draws every copy's
+    # placement per splat; FP64 binned and direct against the oracle
+    w = _small_scene(n_points=(1 << 13) + 9)
+    a = 480 / 270
+    star = lambda n, ch: {"final_kind": "identity", "place": W._place(1.0), "channel": ch,
+                          "n_copies": n, "copy_lo": (-a, -1.0), "copy_hi": (a, 1.0),
+                          "scale": (0.004, 0.01)}
+    w["objects"] = [star(300, 0), star(300, 1), star(200, 2), dict(w["objects"][0], channel=3)]
+    ref = orc.chaos_scene(w["system"], w["objects"], w["run"], w["image"])
+    for path in ("direct", "binned"):
+        got = _scene_gpu(api, w, "f64", path)
+        assert rel_l1(got["image"], ref["image"]) <= 1e-4, path
+        assert got["dropped"] == ref["dropped"], path
