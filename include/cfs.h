@@ -364,7 +364,8 @@ typedef struct cfs_batch cfs_batch; /* opaque, library-owned */
  * library-owned device memory, lays out the work queues (one item per
  * blocks_per_item blocks of an instance; one accumulate item per image tile)
  * and allocates the records of the binned splat.  plan NULL = defaults
- * (use cfs_autotune to pick one).  *out receives the handle. */
+ * (blocks_per_item 4, both grids two per compute unit, binned; use
+ * cfs_autotune to pick one).  *out receives the handle. */
 int cfs_batch_create(const cfs_batch_item *items, int32_t n_items,
                      const cfs_plan *plan, cfs_batch **out);
 

@@ -76,7 +76,9 @@ int validate_item(const cfs_batch_item &it, int i) {
 }
 
 int normalise_plan(const cfs_plan *in, int cus, cfs_plan *out) {
-  cfs_plan p{1, 0, 0, CFS_SPLAT_BINNED};
+  // default: four blocks per item (256 random systems: 7.59 ms per graph
+  // launch against 7.76 with one; the accumulate grid barely matters)
+  cfs_plan p{4, 0, 0, CFS_SPLAT_BINNED};
   if (in) p = *in;
   if (p.blocks_per_item < 1 || p.blocks_per_item > 1024)
     return fail(CFS_E_INVALID, "plan.blocks_per_item must be in 1..1024");
