@@ -337,21 +337,24 @@ __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
 // tile's records in those chunks, added into the image -- with a plain
 // read-modify-write when the part is every chunk (the workgroup then owns
 // the tile), with device atomics when several parts share the tile.  Runs
-// are walked by groups of 2^log2g lanes (one run per group, 4 records per
-// lane per 8-byte load from the 4-record boundary below the run start;
-// records outside [start, end) are skipped): the host picks the group size
-// from the mean run length, so short runs keep many runs in flight and long
-// runs are read with coalesced loads.  Every thread of the workgroup calls
-// it; `tile` is kTileElems words of LDS.
-constexpr int kRunsInFlight = 8;
+// are walked by groups of 2^log2g lanes (one run per group, 8 records per
+// lane per 16-byte load from the 8-record boundary below the run start;
+// records outside [start, end) are skipped; a chunk holds a multiple of 8
+// records, so no load leaves it): the group size follows the mean run
+// length, so short runs keep many runs in flight and long runs are read
+// with coalesced loads.  Every thread of the workgroup calls it; `tile` is
+// kTileElems words of LDS.
+constexpr int kRunsInFlight = 4;
+static_assert(kChunkCap % 8 == 0, "chunks hold whole 16-byte record groups");
 
-__device__ inline void count_records(uint32_t *tile, uint2 v, uint32_t at, uint32_t s,
+__device__ inline void count_records(uint32_t *tile, uint4 v, uint32_t at, uint32_t s,
                                      uint32_t e) {
-  const uint32_t r4[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
+  const uint32_t r8[8] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16,
+                          v.z & 0xFFFFu, v.z >> 16, v.w & 0xFFFFu, v.w >> 16};
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < 8; ++m) {
     const uint32_t idx = at + m;
-    if (idx >= s && idx < e) atomicAdd(&tile[r4[m]], 1u);
+    if (idx >= s && idx < e) atomicAdd(&tile[r8[m]], 1u);
   }
 }
 
@@ -368,7 +371,7 @@ __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
   const uint32_t g = 1u << log2g, lane = tid & (g - 1u);
   const uint32_t groups = kAccBlock >> log2g;
   // kRunsInFlight runs per group at a time: their bounds, then the first
-  // 4g records of each, then the counts, so several loads per lane overlap
+  // 8g records of each, then the counts, so several loads per lane overlap
   for (uint32_t c0 = c_lo + (tid >> log2g); c0 < c_hi; c0 += groups * kRunsInFlight) {
     uint32_t s[kRunsInFlight], e[kRunsInFlight];
 #pragma unroll
@@ -384,18 +387,18 @@ __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
       s[u] += base;
       e[u] += base;
     }
-    uint2 v[kRunsInFlight];
+    uint4 v[kRunsInFlight];
 #pragma unroll
     for (int u = 0; u < kRunsInFlight; ++u) {
-      const uint32_t i = (s[u] & ~3u) + 4u * lane;
-      v[u] = i < e[u] ? *reinterpret_cast<const uint2 *>(rec + i) : make_uint2(0u, 0u);
+      const uint32_t i = (s[u] & ~7u) + 8u * lane;
+      v[u] = i < e[u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
     for (int u = 0; u < kRunsInFlight; ++u) {
-      const uint32_t i = (s[u] & ~3u) + 4u * lane;
+      const uint32_t i = (s[u] & ~7u) + 8u * lane;
       count_records(tile, v[u], i, s[u], e[u]);
-      for (uint32_t j = i + 4u * g; j < e[u]; j += 4u * g)
-        count_records(tile, *reinterpret_cast<const uint2 *>(rec + j), j, s[u], e[u]);
+      for (uint32_t j = i + 8u * g; j < e[u]; j += 8u * g)
+        count_records(tile, *reinterpret_cast<const uint4 *>(rec + j), j, s[u], e[u]);
     }
   }
   __syncthreads();

@@ -85,13 +85,12 @@ constexpr uint32_t kAccTargetGroups = 512;
 constexpr uint32_t kAccTargetSkip = 4 * kAccTargetGroups;
 
 // Lanes per run of the count accumulate, 2^log2g: the smallest group whose
-// one pass of 4 records per lane covers a run of the mean length that starts
-// just above a 4-record boundary (longer runs take further passes; larger
-// groups measured slower).
+// one pass of 8 records per lane covers a run of the mean length plus three
+// (longer runs take further passes; larger groups measured slower).
 __host__ __device__ inline uint32_t run_lanes_log2(uint64_t mean_run) {
   const uint64_t need = mean_run + 3u;
   uint32_t lg = 0;
-  while (lg < 6 && (4ull << lg) < need) ++lg;
+  while (lg < 5 && (8ull << lg) < need) ++lg;
   return lg;
 }
 

@@ -136,11 +136,11 @@ hipError_t launch_transpose(const uint16_t *in, uint16_t *out, uint32_t rows, ui
 
 void acc_shape(uint64_t records, uint32_t n_chunks, uint32_t n_tiles, uint32_t target,
                uint32_t *parts, uint32_t *log2g) {
-  // mean run length -> lanes per run (a lane loads 4 records)
+  // mean run length -> lanes per run (a lane loads 8 records)
   const uint64_t runs = static_cast<uint64_t>(n_chunks) * (n_tiles ? n_tiles : 1);
   const uint64_t mean = runs ? records / runs : 0;
   uint32_t lg = 0;
-  while (lg < 6 && (4ull << lg) < mean) ++lg;
+  while (lg < 5 && (8ull << lg) < mean) ++lg;
   *log2g = lg;
   // about `target` workgroups, but at least one pass of groups each
   const uint32_t groups = kAccBlock >> lg;
