@@ -63,7 +63,8 @@ class _System(C.Structure):
 class _Run(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32),
                 ("n_points", C.c_uint32), ("point_offset", C.c_uint32),
-                ("n_iters", C.c_uint32), ("burn_in", C.c_uint32)]
+                ("n_iters", C.c_uint32), ("burn_in", C.c_uint32),
+                ("iter_offset", C.c_uint32)]
 
 
 class _Window(C.Structure):
@@ -131,7 +132,23 @@ class _Keep:
 def _run(run):
     return _Run(int(run.get("seed", 0)), int(run.get("instance", 0)),
                 int(run["n_points"]), int(run.get("point_offset", 0)),
-                int(run["n_iters"]), int(run["burn_in"]))
+                int(run["n_iters"]), int(run["burn_in"]), int(run.get("iter_offset", 0)))
+
+
+def _start(run, start, n, d):
+    """Positions of a continued run (iter_offset > 0): a copy of ``start``
+    [N][d] that the oracle reads and overwrites; None for a fresh run."""
+    if not int(run.get("iter_offset", 0)):
+        return None
+    if start is None:
+        raise ValueError("a run with iter_offset > 0 needs start positions")
+    fin = np.array(start, dtype=np.float64, order="C").reshape(n, d)
+    return fin
+
+
+def _splats_per_point(r):
+    b = r.burn_in - r.iter_offset if r.burn_in > r.iter_offset else 0
+    return r.n_iters - min(b, r.n_iters)
 
 
 def _window(img):
@@ -193,25 +210,30 @@ def select_histogram(thresh):
 
 
 def chaos_count(system, run, image, *, want_final=False, want_last=False,
-                want_indices=False, want_splats=False, out=None):
+                want_indices=False, want_splats=False, out=None, start=None):
     """Plain chaos game with a u32 count image [channels][H][W].
 
     Returns a dict with 'image' (accumulated into ``out`` when given) and the
     optional 'final' [N][dim] (FP64), 'last' [N], 'indices' [N][T],
-    'splats' [N][T-B][2] fractional pixel coordinates, and 'dropped'.
+    'splats' [N][S][2] fractional pixel coordinates (S splatted steps of this
+    call), and 'dropped'.  A run with ``iter_offset`` K > 0 continues the
+    points for T more steps from ``start`` [N][dim] (their positions after K
+    steps); 'final' is then always returned.
     """
     lib = _load()
     keep = _Keep(system)
     r = _run(run)
     w = _window(image)
-    N, T, B, d = r.n_points, r.n_iters, r.burn_in, keep.s.dim
+    N, T, d = r.n_points, r.n_iters, keep.s.dim
     img = out if out is not None else np.zeros(
         (w.channels, w.height, w.width), np.uint32)
     assert img.dtype == np.uint32 and img.flags.c_contiguous
-    fin = np.zeros((N, d), np.float64) if want_final else None
+    fin = _start(run, start, N, d)
+    if fin is None and want_final:
+        fin = np.zeros((N, d), np.float64)
     last = np.zeros(N, np.uint8) if want_last else None
     idx = np.zeros((N, T), np.uint8) if want_indices else None
-    spl = np.zeros((N, T - B, 2), np.float64) if want_splats else None
+    spl = np.zeros((N, _splats_per_point(r), 2), np.float64) if want_splats else None
     dropped = np.zeros(1, np.uint64)
     rc = lib.orc_chaos_count(C.byref(keep.s), C.byref(r), C.byref(w), _ptr(img),
                              _ptr(fin), _ptr(last), _ptr(idx), _ptr(spl),
@@ -275,20 +297,23 @@ def chaos_scene(system, objects, run, image, *, want_splats=False, out=None):
 
 
 def chaos_depth(system, run, image, near, *, want_final=False, want_last=False,
-                want_splats=False, depth=None, density=None):
-    """3D chaos game into a u64 depth|index min-buffer and a u32 density."""
+                want_splats=False, depth=None, density=None, start=None):
+    """3D chaos game into a u64 depth|index min-buffer and a u32 density
+    (continued runs as for chaos_count)."""
     lib = _load()
     keep = _Keep(system)
     r = _run(run)
     w = _window(image)
-    N, T, B = r.n_points, r.n_iters, r.burn_in
+    N = r.n_points
     if depth is None:
         depth = np.full((w.height, w.width), np.iinfo(np.uint64).max, np.uint64)
     if density is None:
         density = np.zeros((w.height, w.width), np.uint32)
-    fin = np.zeros((N, 3), np.float64) if want_final else None
+    fin = _start(run, start, N, 3)
+    if fin is None and want_final:
+        fin = np.zeros((N, 3), np.float64)
     last = np.zeros(N, np.uint8) if want_last else None
-    spl = np.zeros((N, T - B, 3), np.float64) if want_splats else None
+    spl = np.zeros((N, _splats_per_point(r), 3), np.float64) if want_splats else None
     dropped = np.zeros(1, np.uint64)
     rc = lib.orc_chaos_depth(C.byref(keep.s), C.byref(r), C.byref(w),
                              C.c_float(near), _ptr(depth), _ptr(density),

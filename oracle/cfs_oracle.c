@@ -162,8 +162,11 @@ typedef struct {
   uint32_t instance;
   uint32_t n_points;
   uint32_t point_offset; /* global id of the first point */
-  uint32_t n_iters;      /* T: map applications per point */
-  uint32_t burn_in;      /* B: iterations 1..B are not splatted */
+  uint32_t n_iters;      /* T: map applications per point in this call */
+  uint32_t burn_in;      /* B: steps 1..B of the whole game are not splatted */
+  uint32_t iter_offset;  /* K: steps taken before this call (0: start from the
+                            initial point; else from final_p, which is then
+                            read as well as written) */
 } orc_run;
 
 typedef struct {
@@ -180,6 +183,24 @@ static void point_stream(const orc_run *r, uint32_t pid, uint32_t block,
   uint32_t key[2] = {(uint32_t)r->seed, (uint32_t)(r->seed >> 32)};
   uint32_t ctr[4] = {pid, block, r->instance, tag};
   orc_philox4x32_10(ctr, key, out);
+}
+
+/* Map draw of global step g >= 1 of point pid: word (g-1) mod 4 of Philox
+ * block (pid, (g-1)/4, instance, 0); the block is fetched at the first step
+ * of a call and whenever a new block starts.  A game cut into calls at any
+ * step therefore draws the same words as one call (Section 3: the chaos
+ * game is one sequence of steps per point). */
+static uint32_t step_draw(const orc_run *r, uint32_t pid, uint32_t g, int first,
+                          uint32_t words[4]) {
+  if (first || (g - 1) % 4 == 0) point_stream(r, pid, (g - 1) / 4, 0, words);
+  return words[(g - 1) % 4];
+}
+
+/* Steps of this call that are not splatted: the part of the burn-in that
+ * lies in it (a call inside the burn-in splats nothing). */
+static uint32_t call_burn_in(const orc_run *r) {
+  const uint32_t b = r->burn_in > r->iter_offset ? r->burn_in - r->iter_offset : 0u;
+  return b < r->n_iters ? b : r->n_iters;
 }
 
 /* Initial point (Section 3: the chaos game "starts with a single point
@@ -336,7 +357,6 @@ static int check_common(const orc_system *s, const orc_run *r, const orc_window 
       if (s->kind[i] != ORC_MAP_AFFINE && s->kind[i] != ORC_MAP_CIRCLE) return ORC_EINVAL;
       if (s->kind[i] == ORC_MAP_CIRCLE && s->dim != 2) return ORC_EINVAL;
     }
-  if (r->burn_in > r->n_iters) return ORC_EINVAL;
   if (w->width < 1 || w->height < 1 || w->channels < 1) return ORC_EINVAL;
   if (!(w->hi[0] > w->lo[0]) || !(w->hi[1] > w->lo[1])) return ORC_EINVAL;
   return orc_thresholds(s->prob, s->n_maps, thresh);
@@ -362,19 +382,22 @@ int orc_chaos_count(const orc_system *s, const orc_run *r, const orc_window *w,
   if (s->final_kind == ORC_FINAL_TWIST_CAMERA) return ORC_EINVAL;
   if (s->compose != 0 && s->compose != 1) return ORC_EINVAL;
   if (s->compose && s->dim != 2) return ORC_EINVAL;
+  if (r->iter_offset && !final_p) return ORC_EINVAL;
   const int d = s->dim;
-  const uint32_t T = r->n_iters, B = r->burn_in;
+  const uint32_t T = r->n_iters, B = call_burn_in(r), K = r->iter_offset;
   const size_t plane = (size_t)w->width * (size_t)w->height;
   uint64_t n_drop = 0;
   for (uint32_t n = 0; n < r->n_points; ++n) {
     uint32_t pid = r->point_offset + n;
     double p[3] = {0, 0, 0};
-    initial_point(r, pid, d, p);
+    if (K)
+      for (int c = 0; c < d; ++c) p[c] = final_p[(size_t)n * d + c];
+    else
+      initial_point(r, pid, d, p);
     uint32_t words[4] = {0, 0, 0, 0};
     int k = 0;
     for (uint32_t t = 1; t <= T; ++t) {
-      if ((t - 1) % 4 == 0) point_stream(r, pid, (t - 1) / 4, 0, words);
-      uint32_t u = words[(t - 1) % 4];
+      uint32_t u = step_draw(r, pid, K + t, t == 1, words);
       k = orc_select(u, thresh, s->n_maps);
       if (idx) idx[(size_t)n * T + (t - 1)] = (uint8_t)k;
       apply_map(s, k, p);
@@ -456,6 +479,7 @@ int orc_chaos_scene(const orc_system *s, const orc_object *obj, int n_obj,
   int rc = check_common(s, r, w, thresh);
   if (rc) return rc;
   if (s->dim != 2 || s->final_kind != ORC_FINAL_IDENTITY || s->compose) return ORC_EINVAL;
+  if (r->iter_offset || r->burn_in > r->n_iters) return ORC_EINVAL;
   if (n_obj < 1 || n_obj > ORC_MAX_OBJECTS) return ORC_EINVAL;
   int any_copies = 0;
   for (int o = 0; o < n_obj; ++o) {
@@ -539,17 +563,20 @@ int orc_chaos_depth(const orc_system *s, const orc_run *r, const orc_window *w,
   int rc = check_common(s, r, w, thresh);
   if (rc) return rc;
   if (s->dim != 3 || s->final_kind != ORC_FINAL_TWIST_CAMERA || s->compose) return ORC_EINVAL;
-  const uint32_t T = r->n_iters, B = r->burn_in;
+  if (r->iter_offset && !final_p) return ORC_EINVAL;
+  const uint32_t T = r->n_iters, B = call_burn_in(r), K = r->iter_offset;
   uint64_t n_drop = 0;
   for (uint32_t n = 0; n < r->n_points; ++n) {
     uint32_t pid = r->point_offset + n;
     double p[3];
-    initial_point(r, pid, 3, p);
+    if (K)
+      for (int c = 0; c < 3; ++c) p[c] = final_p[(size_t)n * 3 + c];
+    else
+      initial_point(r, pid, 3, p);
     uint32_t words[4] = {0, 0, 0, 0};
     int k = 0;
     for (uint32_t t = 1; t <= T; ++t) {
-      if ((t - 1) % 4 == 0) point_stream(r, pid, (t - 1) / 4, 0, words);
-      k = orc_select(words[(t - 1) % 4], thresh, s->n_maps);
+      k = orc_select(step_draw(r, pid, K + t, t == 1, words), thresh, s->n_maps);
       apply_map(s, k, p);
       if (t > B) {
         double q[2], z = 0.0, fx, fy;
@@ -642,6 +669,7 @@ int orc_splat_gauss(const orc_system *s, const orc_run *r, const orc_window *w,
   if (rc) return rc;
   if (s->dim != 2 || s->final_kind != ORC_FINAL_IDENTITY || !(sigma > 0.0) || s->kind)
     return ORC_EINVAL;
+  if (r->iter_offset || r->burn_in > r->n_iters) return ORC_EINVAL;
   const uint32_t T = r->n_iters, B = r->burn_in;
   if (T == B || r->n_points == 0) return ORC_OK;
   const double weight = 1.0 / ((double)r->n_points * (double)(T - B));
@@ -681,6 +709,7 @@ int orc_splat_gauss_backward(const orc_system *s, const orc_run *r,
   if (rc) return rc;
   if (s->dim != 2 || s->final_kind != ORC_FINAL_IDENTITY || !(sigma > 0.0) || s->kind)
     return ORC_EINVAL;
+  if (r->iter_offset || r->burn_in > r->n_iters) return ORC_EINVAL;
   const int n_par = 6;
   for (int i = 0; i < s->n_maps * n_par; ++i) grad[i] = 0.0;
   const uint32_t T = r->n_iters, B = r->burn_in;
