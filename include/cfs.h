@@ -143,16 +143,29 @@ typedef struct cfs_system {
   int32_t compose;        /* CFS_COMPOSE_COPY (default) or CFS_COMPOSE_REUSE */
 } cfs_system;
 
-/* One run over a range of points. */
+/* One run over a range of points.
+ * Continued runs (cfs_chaos_game only; Section 3: a point's chaos game is
+ * one sequence of steps, so it can be cut into calls): with iter_offset
+ * K > 0 every point has already taken K steps, its position after them is
+ * read from final_points (which must be given, in the run's precision) and
+ * overwritten with its position after this call's T further steps; step t
+ * of the call is step K + t of the game (map draw: word (K + t - 1) mod 4
+ * of Philox block (K + t - 1) / 4), and burn_in counts the game's steps, so
+ * a call inside the burn-in splats nothing.  K must be a multiple of 4 (the
+ * kernels draw whole Philox blocks).  A game cut into calls this way gives
+ * the same indices, positions and (summed) image as one call. */
 typedef struct cfs_run {
   uint64_t seed;          /* Philox key */
   uint32_t instance;      /* third counter word (batched instance id) */
   uint32_t n_points;      /* N */
   uint32_t point_offset;  /* global id of the first point; offset + N <= 2^32 */
   uint32_t n_iters;       /* T map applications per point, 1 .. 2^20 */
-  uint32_t burn_in;       /* B <= T: iterations 1..B are not splatted */
+  uint32_t burn_in;       /* B: steps 1..B of the game are not splatted (B <= T
+                             except in cfs_chaos_game) */
   int32_t precision;      /* CFS_PREC_F32 or CFS_PREC_F64 */
   int32_t splat_path;     /* CFS_SPLAT_AUTO / _DIRECT / _BINNED (count images) */
+  uint32_t iter_offset;   /* K: steps already taken (0 = a fresh game); a
+                             multiple of 4, at most 2^30 */
 } cfs_run;
 
 /* An output image in device memory. */

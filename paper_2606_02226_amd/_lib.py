@@ -49,7 +49,8 @@ class CfsRun(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("instance", C.c_uint32),
                 ("n_points", C.c_uint32), ("point_offset", C.c_uint32),
                 ("n_iters", C.c_uint32), ("burn_in", C.c_uint32),
-                ("precision", C.c_int32), ("splat_path", C.c_int32)]
+                ("precision", C.c_int32), ("splat_path", C.c_int32),
+                ("iter_offset", C.c_uint32)]
 
 
 class CfsImage(C.Structure):

@@ -61,7 +61,8 @@ def run_struct(run, precision="f32", splat_path="auto"):
     return CfsRun(int(run.get("seed", 0)), int(run.get("instance", 0)),
                   int(run["n_points"]), int(run.get("point_offset", 0)),
                   int(run["n_iters"]), int(run["burn_in"]),
-                  _lib.PRECISIONS[precision], _lib.SPLAT_PATHS[splat_path])
+                  _lib.PRECISIONS[precision], _lib.SPLAT_PATHS[splat_path],
+                  int(run.get("iter_offset", 0)))
 
 
 class Image:
@@ -133,6 +134,9 @@ def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
     ``system`` is a workload system dict or a :class:`System`; ``final``
     (float32/float64 [N][dim]), ``last`` (uint8 [N]) and ``indices``
     (uint8 [N][T]) are optional device tensors.  The image accumulates.
+    A run with ``iter_offset`` K > 0 (a multiple of 4) continues the points
+    from the positions in ``final`` (after K steps) and leaves them there
+    after its own steps.
     """
     lib = _lib.load()
     sysc = system if isinstance(system, System) else System(system)

@@ -105,8 +105,9 @@ int validate_run(const cfs_run *r) {
   if (!r) return fail(CFS_E_INVALID, "run is NULL");
   if (r->n_iters < 1 || r->n_iters > (1u << 20))
     return fail(CFS_E_INVALID, "n_iters must be in 1..2^20 (got %u)", r->n_iters);
-  if (r->burn_in > r->n_iters)
-    return fail(CFS_E_INVALID, "burn_in %u exceeds n_iters %u", r->burn_in, r->n_iters);
+  if (r->iter_offset % 4 != 0 || r->iter_offset > (1u << 30))
+    return fail(CFS_E_INVALID, "iter_offset must be a multiple of 4 in 0..2^30 (got %u)",
+                r->iter_offset);
   if (static_cast<uint64_t>(r->point_offset) + r->n_points > (1ull << 32))
     return fail(CFS_E_INVALID, "point_offset + n_points exceeds 2^32");
   if (r->precision != CFS_PREC_F32 && r->precision != CFS_PREC_F64)
@@ -154,6 +155,24 @@ Window make_window(const cfs_image *img, bool by_index) {
   return w;
 }
 
+int validate_fresh_run(const cfs_run *r) {
+  const int rc = validate_run(r);
+  if (rc) return rc;
+  if (r->iter_offset)
+    return fail(CFS_E_UNSUPPORTED, "continued runs (iter_offset %u) are for cfs_chaos_game only",
+                r->iter_offset);
+  if (r->burn_in > r->n_iters)
+    return fail(CFS_E_INVALID, "burn_in %u exceeds n_iters %u", r->burn_in, r->n_iters);
+  return CFS_OK;
+}
+
+cfs_run call_run(const cfs_run *r) {
+  cfs_run c = *r;
+  const uint32_t b = r->burn_in > r->iter_offset ? r->burn_in - r->iter_offset : 0u;
+  c.burn_in = b < r->n_iters ? b : r->n_iters;
+  return c;
+}
+
 RunArgs make_run_args(const cfs_run *r) {
   RunArgs ra{};
   ra.k0 = static_cast<uint32_t>(r->seed);
@@ -163,6 +182,7 @@ RunArgs make_run_args(const cfs_run *r) {
   ra.point_offset = r->point_offset;
   ra.n_iters = r->n_iters;
   ra.burn_in = r->burn_in;
+  ra.iter_block = r->iter_offset / 4;
   return ra;
 }
 
@@ -364,7 +384,7 @@ SceneArgs pack_objects(const cfs_object *objects, int32_t n_objects) {
 int validate_scene(const cfs_system *sys, const cfs_object *objects, int32_t n_objects,
                    const cfs_run *run, const cfs_image *img) {
   int rc = validate_system(sys);
-  if (!rc) rc = validate_run(run);
+  if (!rc) rc = validate_fresh_run(run);
   if (!rc) rc = validate_window(img);
   if (rc) return rc;
   if (sys->dim != 2) return fail(CFS_E_INVALID, "a scene's primitive must be 2D");
@@ -393,18 +413,25 @@ bool scene_binned(const cfs_run *run, const cfs_image *img, int32_t n_objects) {
 extern "C" size_t cfs_chaos_game_workspace(const cfs_system *sys, const cfs_run *run,
                                            const cfs_image *img) {
   if (validate_system(sys) || validate_run(run) || validate_window(img)) return 0;
-  if (!use_binned(run, img)) return 0;
-  return binned_workspace(run, img);
+  const cfs_run cr = call_run(run);
+  if (!use_binned(&cr, img)) return 0;
+  return binned_workspace(&cr, img);
 }
 
-extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
+extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, const cfs_image *img,
                               void *final_points, uint8_t *last_index, uint8_t *indices,
                               void *workspace, size_t workspace_bytes, void *stream) {
   clear_error();
   int rc = validate_system(sys);
-  if (!rc) rc = validate_run(run);
+  if (!rc) rc = validate_run(run_in);
   if (!rc) rc = validate_window(img);
   if (rc) return rc;
+  if (run_in->iter_offset && !final_points)
+    return fail(CFS_E_INVALID, "a continued run (iter_offset %u) reads its start from final_points",
+                run_in->iter_offset);
+  // this call's view of the run: the part of the burn-in inside it
+  const cfs_run call = call_run(run_in);
+  const cfs_run *run = &call;
   if (run->splat_path < CFS_SPLAT_AUTO || run->splat_path > CFS_SPLAT_BINNED)
     return fail(CFS_E_INVALID, "unknown splat_path %d", run->splat_path);
   ChaosJob job;

@@ -52,7 +52,7 @@ void free_batch(cfs_batch *b) {
 
 int validate_item(const cfs_batch_item &it, int i) {
   int rc = validate_system(&it.sys);
-  if (!rc) rc = validate_run(&it.run);
+  if (!rc) rc = validate_fresh_run(&it.run);
   if (!rc) rc = validate_window(&it.img);
   if (rc) return fail(rc, "batch item %d: %s", i, cfs_last_error());
   if (it.sys.dim != 2 || it.sys.final_kind != CFS_FINAL_IDENTITY)

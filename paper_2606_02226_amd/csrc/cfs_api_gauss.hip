@@ -17,7 +17,7 @@ size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 int validate_gauss(const cfs_system *sys, const cfs_run *run, const cfs_image *img, float sigma) {
   int rc = validate_system(sys);
-  if (!rc) rc = validate_run(run);
+  if (!rc) rc = validate_fresh_run(run);
   if (!rc) rc = validate_window(img);
   if (rc) return rc;
   if (sys->dim != 2 || sys->final_kind != CFS_FINAL_IDENTITY)

@@ -13,6 +13,11 @@ int device_status(hipError_t e, const char *what);
 int make_thresholds(const double *prob, int n, uint64_t *thresh);
 int validate_system(const cfs_system *s);
 int validate_run(const cfs_run *r);
+// Entry points without continued runs: iter_offset 0 and burn_in <= n_iters.
+int validate_fresh_run(const cfs_run *r);
+// The run as one cfs_chaos_game call sees it: burn_in reduced to the part of
+// the game's burn-in that lies in this call's steps.
+cfs_run call_run(const cfs_run *r);
 int validate_window(const cfs_image *img);
 Window make_window(const cfs_image *img, bool by_index);
 RunArgs make_run_args(const cfs_run *r);

@@ -94,9 +94,9 @@ __device__ inline void flush_chunk(uint32_t *stage, uint32_t *cnt, uint32_t *wsu
 // game of each lane's point with the binned splat.  table/th hold the map
 // table in LDS; cnt[0 .. n_tiles) must be zero on entry and is zero on exit.
 // Every thread of the workgroup calls it (it holds barriers).  GENERAL
-// compiles the circle-map and reuse branches (`flags`); without it they are
-// compiled out, which keeps the affine copy-transform loop at its register
-// count.
+// compiles the circle-map and reuse branches (`flags`) and continued runs
+// (RunArgs::iter_block); without it they are compiled out, which keeps the
+// affine copy-transform loop at its register count.
 template <typename real, int DIM, int FINAL, int SEL, bool GENERAL = true>
 __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_maps, int n_search,
                                    int flags, const Window &win, const RunArgs &ra,
@@ -110,15 +110,21 @@ __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_
   const uint32_t T = ra.n_iters, B = ra.burn_in;
   const uint32_t plane = static_cast<uint32_t>(win.width) * static_cast<uint32_t>(win.height);
 
+  // continued runs take the general variant (the fast one keeps its
+  // registers: a fresh game from the initial point)
   real p[DIM];
-  initial_point<real, DIM>(pid, ra.instance, ra.k0, ra.k1, p);
+  if constexpr (GENERAL)
+    start_point<real, DIM>(ra, pid, n, active, out.final_points, p);
+  else
+    initial_point<real, DIM>(pid, ra.instance, ra.k0, ra.k1, p);
+  const uint32_t blk0 = GENERAL ? ra.iter_block : 0u;
   int k = 0;
   uint32_t dropped = 0;
   int slot = 0;
   uint32_t chunk = block * ba.flushes;
 
   for (uint32_t t0 = 0; t0 < T; t0 += 4) {
-    const Block4 blk = philox10(pid, t0 >> 2, ra.instance, 0u, ra.k0, ra.k1);
+    const Block4 blk = philox10(pid, (t0 >> 2) + blk0, ra.instance, 0u, ra.k0, ra.k1);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t t = t0 + j + 1;
@@ -232,13 +238,13 @@ __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_m
   const uint32_t pid = ra.point_offset + (active ? n : 0u);
   const uint32_t T = ra.n_iters, B = ra.burn_in;
   real p[3];
-  initial_point<real, 3>(pid, ra.instance, ra.k0, ra.k1, p);
+  start_point<real, 3>(ra, pid, n, active, out.final_points, p);
   int k = 0;
   uint32_t dropped = 0;
   int slot = 0;
   uint32_t chunk = block * ba.flushes;
   for (uint32_t t0 = 0; t0 < T; t0 += 4) {
-    const Block4 blk = philox10(pid, t0 >> 2, ra.instance, 0u, ra.k0, ra.k1);
+    const Block4 blk = philox10(pid, (t0 >> 2) + ra.iter_block, ra.instance, 0u, ra.k0, ra.k1);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t t = t0 + j + 1;

@@ -58,6 +58,25 @@ __device__ __forceinline__ void initial_point(uint32_t pid, uint32_t instance,
   if constexpr (DIM == 3) p[2] = static_cast<real>(w.w2 >> 8) * s;
 }
 
+// Starting position of point n: the initial point of a fresh game, or, for
+// a continued run, the position stored in `state` after the steps already
+// taken (lanes past the run's end read nothing and take zeros).
+template <typename real, int DIM>
+__device__ __forceinline__ void start_point(const RunArgs &ra, uint32_t pid, uint32_t n,
+                                            bool active, const void *state, real p[DIM]) {
+  if (ra.iter_block) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) p[c] = static_cast<real>(0);
+    if (active) {
+      const real *s = static_cast<const real *>(state) + static_cast<size_t>(n) * DIM;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) p[c] = s[c];
+    }
+  } else {
+    initial_point<real, DIM>(pid, ra.instance, ra.k0, ra.k1, p);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Selection.  Equal probabilities: k = floor(u n / 2^32) (one mul_hi).
 // Otherwise k = the number of finite thresholds <= u (the inverse CDF),

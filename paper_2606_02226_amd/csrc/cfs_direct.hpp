@@ -20,13 +20,18 @@ __device__ void chaos_direct_point(const real *table, const uint32_t *th, int n_
   const uint32_t T = ra.n_iters, B = ra.burn_in;
   const size_t plane = static_cast<size_t>(win.width) * static_cast<size_t>(win.height);
 
+  // continued runs take the general variant, as in chaos_binned_block
   real p[DIM];
-  initial_point<real, DIM>(pid, ra.instance, ra.k0, ra.k1, p);
+  if constexpr (GENERAL)
+    start_point<real, DIM>(ra, pid, n, true, out.final_points, p);
+  else
+    initial_point<real, DIM>(pid, ra.instance, ra.k0, ra.k1, p);
+  const uint32_t blk0 = GENERAL ? ra.iter_block : 0u;
   int k = 0;
   uint32_t dropped = 0;
 
   for (uint32_t t0 = 0; t0 < T; t0 += 4) {
-    const Block4 blk = philox10(pid, t0 >> 2, ra.instance, 0u, ra.k0, ra.k1);
+    const Block4 blk = philox10(pid, (t0 >> 2) + blk0, ra.instance, 0u, ra.k0, ra.k1);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t t = t0 + j + 1;

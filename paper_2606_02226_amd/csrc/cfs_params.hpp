@@ -52,7 +52,9 @@ struct RunArgs {
   uint32_t n_points;
   uint32_t point_offset;
   uint32_t n_iters;
-  uint32_t burn_in;
+  uint32_t burn_in;     // steps of this call that are not splatted
+  uint32_t iter_block;  // Philox blocks of steps already taken (iter_offset / 4); > 0:
+                        // a continued run, started from Outputs::final_points
 };
 
 // Binned integer splat: a workgroup of kBinBlock lanes (two per CU fit in

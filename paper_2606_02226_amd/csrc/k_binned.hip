@@ -189,9 +189,10 @@ static hipError_t launch_binned_typed(const ChaosJob &j, hipStream_t s) {
   }();
   const uint32_t blocks = (j.ra.n_points + kBinBlock - 1) / kBinBlock;
   mark_phase(j.ev, 0, s);
-  // circle maps and reuse composition are 2D only
-  if (DIM == 2 && mt.flags != 0)
-    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, DIM == 2>), dim3(blocks),
+  // circle maps, reuse composition (2D only) and continued runs take the
+  // general variant
+  if (mt.flags != 0 || j.ra.iter_block != 0)
+    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, true>), dim3(blocks),
                        dim3(kBinBlock), 0, s, mt, j.win, j.ra, j.fa, j.ba, j.out);
   else
     hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, false>), dim3(blocks),

@@ -33,9 +33,10 @@ static hipError_t launch_typed(const ChaosJob &j, hipStream_t s) {
   const MapTable<DIM> &mt = [&]() -> const MapTable<DIM> & {
     if constexpr (DIM == 2) return j.mt2; else return j.mt3;
   }();
-  // circle maps and reuse composition are 2D only
-  if (DIM == 2 && mt.flags != 0)
-    hipLaunchKernelGGL((k_chaos<real, DIM, FINAL, EQUAL, DEPTH, DIM == 2>), dim3(blocks),
+  // circle maps, reuse composition (2D only) and continued runs take the
+  // general variant
+  if (mt.flags != 0 || j.ra.iter_block != 0)
+    hipLaunchKernelGGL((k_chaos<real, DIM, FINAL, EQUAL, DEPTH, true>), dim3(blocks),
                        dim3(kChaosBlock), 0, s, mt, j.win, j.ra, j.fa, j.img, j.density,
                        j.near_plane, j.out);
   else

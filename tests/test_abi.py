@@ -63,8 +63,8 @@ def _system(L, dim=2, n=3, A=None, b=None, prob=None, final_kind=0):
     return s, keep
 
 
-def _run(L, n_points=10, n_iters=8, burn_in=2, precision=0, offset=0):
-    return L.CfsRun(0, 0, n_points, offset, n_iters, burn_in, precision, 0)
+def _run(L, n_points=10, n_iters=8, burn_in=2, precision=0, offset=0, iter_offset=0):
+    return L.CfsRun(0, 0, n_points, offset, n_iters, burn_in, precision, 0, iter_offset)
 
 
 def _image(L, kind=0, W=16, H=16, ch=1, lo=(0, 0), hi=(1, 1)):
@@ -88,7 +88,8 @@ CASES = [
     ("swirl3d", dict(sys=dict(dim=3, final_kind=1)), "needs dim 2"),
     ("camera2d", dict(sys=dict(final_kind=2)), "needs dim 3"),
     ("iters0", dict(run=dict(n_iters=0)), "n_iters must be"),
-    ("burn", dict(run=dict(burn_in=9)), "burn_in"),
+    ("iteroff", dict(run=dict(iter_offset=6)), "iter_offset must be a multiple of 4"),
+    ("iterbig", dict(run=dict(iter_offset=(1 << 30) + 4)), "iter_offset must be a multiple of 4"),
     ("offset", dict(run=dict(offset=2**32 - 5)), "exceeds 2^32"),
     ("prec", dict(run=dict(precision=7)), "precision"),
     ("width", dict(img=dict(W=0)), "image size"),
@@ -355,3 +356,28 @@ def test_binned_image_size_limit(L):
                             None)
     assert rc == L.CFS_E_UNSUPPORTED
     assert "at most 33554432 elements" in lib.cfs_last_error().decode()
+
+
+def test_continued_run_rules(L):
+    # a continued run needs final_points (its start) and is for cfs_chaos_game
+    # only; burn_in beyond n_iters is refused where runs cannot be continued
+    lib = L.load()
+    s, keep = _system(L)
+    img = _image(L)
+    img.data = C.c_void_p(256)  # never dereferenced: the calls fail first
+    r = _run(L, iter_offset=8)
+    rc = lib.cfs_chaos_game(C.byref(s), C.byref(r), C.byref(img), None, None, None, None, 0,
+                            None)
+    assert rc == L.CFS_E_INVALID
+    assert "reads its start from final_points" in lib.cfs_last_error().decode()
+    dens = _image(L, kind=1)
+    dens.data = C.c_void_p(256)
+    rc = lib.cfs_splat(C.byref(s), C.byref(r), C.byref(dens), C.c_float(1.0), None, 0, None,
+                       0, None)
+    assert rc == L.CFS_E_UNSUPPORTED
+    assert "cfs_chaos_game only" in lib.cfs_last_error().decode()
+    r = _run(L, burn_in=9)
+    rc = lib.cfs_splat(C.byref(s), C.byref(r), C.byref(dens), C.c_float(1.0), None, 0, None,
+                       0, None)
+    assert rc == L.CFS_E_INVALID
+    assert "exceeds n_iters" in lib.cfs_last_error().decode()
