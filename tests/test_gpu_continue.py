@@ -71,13 +71,14 @@ def test_continued_call_matches_oracle(api, orc):
     assert np.max(np.abs(fin.cpu().numpy() - ref["final"])) <= 1e-9
 
 
-def test_depth_game_cut(api):
+@pytest.mark.parametrize("path", ["direct", "binned"])
+def test_depth_game_cut(api, path):
     w = W.menger(n_points=(1 << 14) + 5, side=256)
     run = w["run"]
     T = run["n_iters"]
 
     def depth_game(r, fin, img):
-        api.chaos_game(w["system"], r, img, precision="f64", final=fin, splat_path="binned")
+        api.chaos_game(w["system"], r, img, precision="f64", final=fin, splat_path=path)
         torch.cuda.synchronize()
 
     whole = api.Image(w["image"], device=_dev()).clear()
@@ -86,7 +87,8 @@ def test_depth_game_cut(api):
     img = api.Image(w["image"], device=_dev()).clear()
     f = torch.zeros_like(fw)
     depth_game(dict(run, n_iters=8), f, img)
-    depth_game(dict(run, n_iters=T - 8, iter_offset=8), f, img)
+    depth_game(dict(run, n_iters=4, iter_offset=8), f, img)
+    depth_game(dict(run, n_iters=T - 12, iter_offset=12), f, img)
     a, b = img.to_numpy(), whole.to_numpy()
     assert np.array_equal(a["depth"], b["depth"]) and np.array_equal(a["density"], b["density"])
     assert torch.equal(f, fw)
