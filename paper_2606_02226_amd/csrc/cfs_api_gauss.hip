@@ -78,7 +78,7 @@ extern "C" size_t cfs_splat_workspace(const cfs_system *sys, const cfs_run *run,
   if (validate_gauss(sys, run, img, sigma_px)) return 0;
   if (run->n_iters == run->burn_in || run->n_points == 0) return 0;
   const GaussPlan p = gauss_plan(gauss_slice(run), run->n_iters, run->burn_in, img->width, img->height);
-  return align_up(p.records_bytes) + 2 * align_up(p.table_bytes);
+  return align_up(p.records_bytes) + 2 * align_up(p.table_bytes) + align_up(p.sums_bytes);
 }
 
 extern "C" int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
@@ -118,6 +118,8 @@ extern "C" int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_im
     char *tables = static_cast<char *>(workspace) + align_up(p.records_bytes);
     j.gb.chunk_start = reinterpret_cast<uint32_t *>(tables);
     j.gb.tile_start = reinterpret_cast<uint32_t *>(tables + align_up(p.table_bytes));
+    j.gb.tile_sums = reinterpret_cast<uint32_t *>(tables + 2 * align_up(p.table_bytes));
+    j.gb.n_rb = p.n_rb;
     j.gb.n_chunks = no_splats ? 0 : p.n_chunks;
     j.gb.flushes = p.flushes;
     j.gb.n_tiles = p.n_tiles;
@@ -135,9 +137,9 @@ namespace {
 
 // Backward workspace layout: the gradient partials of every sweep workgroup
 // of the run, then, reused by every launch slice, the slice's records, their
-// ids, the two run tables and the splat gradients S.
+// ids, the two run tables, their column sums and the splat gradients S.
 struct BwdLayout {
-  size_t partials, records, ids, table, s, total;
+  size_t partials, records, ids, table, sums, s, total;
 };
 
 BwdLayout bwd_layout(const cfs_system *sys, const cfs_run *run, const cfs_image *img) {
@@ -151,9 +153,10 @@ BwdLayout bwd_layout(const cfs_system *sys, const cfs_run *run, const cfs_image 
     l.records = align_up(p.records_bytes);
     l.ids = align_up(static_cast<size_t>(p.n_chunks) * kGCap * sizeof(uint16_t));
     l.table = align_up(p.table_bytes);
+    l.sums = align_up(p.sums_bytes);
     l.s = align_up(static_cast<size_t>(slice) * (run->n_iters - run->burn_in) * sizeof(float2));
   }
-  l.total = l.partials + l.records + l.ids + 2 * l.table + l.s;
+  l.total = l.partials + l.records + l.ids + 2 * l.table + l.sums + l.s;
   return l;
 }
 
@@ -199,7 +202,8 @@ extern "C" int cfs_splat_backward(const cfs_system *sys, const cfs_run *run, con
   job.gb.ids = reinterpret_cast<uint16_t *>(p + l.records);
   job.gb.chunk_start = reinterpret_cast<uint32_t *>(p + l.records + l.ids);
   job.gb.tile_start = reinterpret_cast<uint32_t *>(p + l.records + l.ids + l.table);
-  job.S = reinterpret_cast<float2 *>(p + l.records + l.ids + 2 * l.table);
+  job.gb.tile_sums = reinterpret_cast<uint32_t *>(p + l.records + l.ids + 2 * l.table);
+  job.S = reinterpret_cast<float2 *>(p + l.records + l.ids + 2 * l.table + l.sums);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const RunArgs ra = make_run_args(run);
   const bool splats = run->n_iters > run->burn_in;
@@ -214,6 +218,7 @@ extern "C" int cfs_splat_backward(const cfs_system *sys, const cfs_run *run, con
     j.gb.n_chunks = splats ? gpl.n_chunks : 0;
     j.gb.flushes = gpl.flushes;
     j.gb.n_tiles = gpl.n_tiles;
+    j.gb.n_rb = gpl.n_rb;
     j.ck.ckpt = const_cast<float *>(ckpt) + 2 * static_cast<size_t>(done);
     j.ck.every = ckpt_every;
     j.ck.stride = run->n_points;

@@ -96,7 +96,8 @@ struct GaussJob {
 struct GaussPlan {
   uint32_t blocks, flushes, n_chunks, n_tiles;
   int32_t tiles_x, tiles_y;
-  size_t records_bytes, table_bytes;
+  uint32_t n_rb;  // 64-chunk blocks of the column sums
+  size_t records_bytes, table_bytes, sums_bytes;
 };
 GaussPlan gauss_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, int width, int height);
 hipError_t launch_splat_forward(const GaussJob &job, hipStream_t stream);

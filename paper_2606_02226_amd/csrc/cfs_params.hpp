@@ -120,6 +120,11 @@ constexpr int kGTileLog = 5;
 constexpr int kGTile = 1 << kGTileLog;
 constexpr int kGMaxTiles = 2048;
 constexpr int kGAccBlock = 256;
+// Per-tile Gaussian kernels: at most this many workgroups per tile, each
+// taking an equal share of the chunks; a tile uses as many of them as its
+// record total asks for at kGPartTarget workgroups for the whole launch.
+constexpr uint32_t kGMaxParts = 64;
+constexpr uint32_t kGPartTarget = 4096;
 constexpr int kGBwdBlock = 256;
 constexpr int kMaxSeg = 16;  // longest checkpoint segment
 
@@ -137,7 +142,8 @@ struct GaussBin {
   uint16_t *ids;         // backward only: each record's slot before sorting (or null)
   uint32_t *chunk_start; // [n_chunks][n_tiles + 1] as the chunks write them
   uint32_t *tile_start;  // [n_tiles + 1][n_chunks] transposed for the accumulate
-  uint32_t n_chunks, flushes, n_tiles;
+  uint32_t *tile_sums;   // [n_tiles + 1][n_rb]: column sums of 64-chunk blocks (record totals)
+  uint32_t n_chunks, flushes, n_tiles, n_rb;
 };
 
 struct GaussCkpt {

@@ -206,39 +206,82 @@ __device__ __forceinline__ void tap_weights(float x, int i0, int lo, int hi, con
   }
 }
 
+// The part of its tile that workgroup b of a per-tile launch takes.  Each
+// tile has p_max consecutive workgroups (consecutive blocks go to different
+// XCDs, so the parts of a dense tile spread over the chip); the tile uses
+// ceil(total / per_part) of them, at most p_max, each with an equal share of
+// the chunks, and walks its runs with groups of 2^log2g lanes
+// where 2^log2g is the first power of two at least the tile's mean run.
+// Returns false (the same in every lane) for a workgroup the tile does not
+// use.  `sums` holds the transpose's column sums of 64-chunk blocks.
+struct TilePart {
+  uint32_t t, c_lo, c_hi, log2g;
+};
+__device__ inline bool gauss_tile_part(const uint32_t *__restrict__ sums, uint32_t n_rb,
+                                       uint32_t n_chunks, uint32_t p_max, uint32_t per_part,
+                                       TilePart *tp) {
+  __shared__ uint32_t red[kGAccBlock / 64];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t t = blockIdx.x / p_max, part = blockIdx.x % p_max;
+  const uint32_t *lo = sums + static_cast<size_t>(t) * n_rb, *hi = lo + n_rb;
+  uint32_t s = 0;
+  for (uint32_t b = tid; b < n_rb; b += kGAccBlock) s += hi[b] - lo[b];
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  uint32_t total = 0;
+#pragma unroll
+  for (int w = 0; w < kGAccBlock / 64; ++w) total += red[w];
+  const uint32_t parts = min(p_max, (total + per_part - 1) / per_part);
+  if (part >= parts) return false;
+  const uint32_t mean = total / n_chunks;
+  uint32_t lg = 0;
+  while (lg < 6 && (1u << lg) < mean) ++lg;
+  tp->t = t;
+  tp->c_lo = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * part / parts);
+  tp->c_hi = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * (part + 1) / parts);
+  tp->log2g = lg;
+  return true;
+}
+
 // One workgroup per (tile, chunk range): the records of its own tile only
-// (binned by their first tap, so every footprint starts inside the tile and
-// ends at most TAPS - 1 pixels past its right and lower edges) are read once
-// and their taps summed into an LDS tile with that halo.  The LDS sums are
+// (binned by their first tap, so every footprint starts at most TAPS - 1
+// pixels left of or above the tile, off the image there, and ends at most
+// TAPS - 1 pixels past its right and lower edges) are read once and their
+// taps summed into an LDS tile with those margins.  The LDS sums are
 // integers: each tap adds round(g(dx) g(dy) 2^31) to a 64-bit counter (LDS
 // integer atomics run far faster than floating-point ones, and integer sums
 // do not depend on their order), so a pixel holds its tap sum to 2^-31 per
-// tap.  The tile plus halo is then scaled by 2^-31 / (N (T - B)) and added
+// tap.  Every tap adds, also those of weight 0, so the loop has no branches
+// and its LDS addresses are one base plus constant offsets.  The tile plus
+// its right and lower halo is then scaled by 2^-31 / (N (T - B)) and added
 // into the density with device float atomics (neighbouring tiles and the
 // other chunk ranges of the tile add into the same pixels).  Runs are walked
 // by groups of 2^log2g lanes, one record per lane.
 template <int TAPS>
 __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *__restrict__ rec,
                                                                  const uint32_t *__restrict__ tile_start,
-                                                                 uint32_t n_chunks, GaussParams gp,
-                                                                 uint32_t parts, uint32_t log2g,
+                                                                 const uint32_t *__restrict__ sums,
+                                                                 uint32_t n_rb, uint32_t n_chunks,
+                                                                 uint32_t p_max, uint32_t per_part,
+                                                                 GaussParams gp,
                                                                  float *__restrict__ dens) {
-  constexpr int H = kGTile + TAPS - 1;  // tile plus halo, per axis
-  __shared__ unsigned long long acc[H * H];
+  constexpr int H = kGTile + TAPS - 1;  // tile plus right and lower halo, per axis
+  constexpr int M = TAPS - 1;           // margin left of and above the tile
+  constexpr int HM = H + M;
+  __shared__ unsigned long long acc[HM * HM];
+  TilePart tp;
+  if (!gauss_tile_part(sums, n_rb, n_chunks, p_max, per_part, &tp)) return;
   const uint32_t tid = threadIdx.x;
-  const uint32_t item = xcd_item(blockIdx.x, gridDim.x);
-  const uint32_t t = item / parts, part = item % parts;
-  const uint32_t c_lo = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * part / parts);
-  const uint32_t c_hi = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * (part + 1) / parts);
-  const int tx = t % gp.tiles_x, ty = t / gp.tiles_x;
+  const int tx = tp.t % gp.tiles_x, ty = tp.t / gp.tiles_x;
   const int x0 = tx * kGTile, y0 = ty * kGTile;
   const int xhi = min(x0 + H, gp.width), yhi = min(y0 + H, gp.height);
-  for (uint32_t i = tid; i < H * H; i += kGAccBlock) acc[i] = 0ull;
+  for (uint32_t i = tid; i < HM * HM; i += kGAccBlock) acc[i] = 0ull;
   __syncthreads();
-  const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
+  const uint32_t *row0 = tile_start + static_cast<size_t>(tp.t) * n_chunks;
   const uint32_t *row1 = row0 + n_chunks;
-  const uint32_t g = 1u << log2g, lane = tid & (g - 1u), groups = kGAccBlock >> log2g;
-  for (uint32_t c = c_lo + (tid >> log2g); c < c_hi; c += groups) {
+  const uint32_t g = 1u << tp.log2g, lane = tid & (g - 1u), groups = kGAccBlock >> tp.log2g;
+  for (uint32_t c = tp.c_lo + (tid >> tp.log2g); c < tp.c_hi; c += groups) {
     const uint32_t s = row0[c], e = row1[c];
     for (uint32_t i = s + lane; i < e; i += g) {
       const float2 r = rec[i];
@@ -248,15 +291,13 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
       float gx[TAPS], gy[TAPS];
       tap_weights<TAPS>(r.x, i0, x0, xhi, gp, gx);
       tap_weights<TAPS>(r.y, j0, y0, yhi, gp, gy);
+      unsigned long long *base = acc + (j0 - y0 + M) * HM + (i0 - x0 + M);
 #pragma unroll
       for (int b = 0; b < TAPS; ++b) {
-        if (gy[b] == 0.0f) continue;
         const float wy = gy[b] * 2147483648.0f;  // 2^31; g <= 1 per axis
 #pragma unroll
         for (int a = 0; a < TAPS; ++a)
-          if (gx[a] != 0.0f)
-            atomicAdd(&acc[(j0 + b - y0) * H + (i0 + a - x0)],
-                      static_cast<unsigned long long>(__float2uint_rn(gx[a] * wy)));
+          atomicAdd(base + b * HM + a, static_cast<unsigned long long>(__float2uint_rn(gx[a] * wy)));
       }
     }
   }
@@ -264,7 +305,7 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
   const double unit = static_cast<double>(gp.weight) * 0x1p-31;
   for (uint32_t i = tid; i < H * H; i += kGAccBlock) {
     const int px = x0 + static_cast<int>(i % H), py = y0 + static_cast<int>(i / H);
-    const unsigned long long v = acc[i];
+    const unsigned long long v = acc[(i / H + M) * HM + i % H + M];
     if (px < gp.width && py < gp.height && v != 0ull)
       atomicAdd(dens + static_cast<size_t>(py) * gp.width + px,
                 static_cast<float>(static_cast<double>(v) * unit));
@@ -320,22 +361,21 @@ __device__ __forceinline__ void splat_grad_px(float x, float y, const GaussParam
 // Per record of one tile and chunk range: the gradient of the loss with
 // respect to the splatted position, from an LDS copy of the tile's upstream
 // gradient with the same halo as the forward accumulate, written to
-// S[iteration - B - 1][point] (points of the launch slice).  One workgroup
-// per (tile, chunk range); groups of 2^log2g lanes per run.
+// S[iteration - B - 1][point] (points of the launch slice).  Workgroups,
+// tile parts and lane groups as in the forward accumulate.
 template <int TAPS>
 __global__ __launch_bounds__(kGAccBlock) void k_splat_grad_tiles(
     const float2 *__restrict__ rec, const uint16_t *__restrict__ ids,
-    const uint32_t *__restrict__ tile_start, uint32_t n_chunks, uint32_t flushes, uint32_t points,
-    GaussParams gp, uint32_t parts, uint32_t log2g, const float *__restrict__ G,
-    float2 *__restrict__ S) {
+    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ sums, uint32_t n_rb,
+    uint32_t n_chunks, uint32_t p_max, uint32_t per_part, uint32_t flushes, uint32_t points,
+    GaussParams gp,
+    const float *__restrict__ G, float2 *__restrict__ S) {
   constexpr int H = kGTile + TAPS - 1;
   __shared__ float g[H * H];
+  TilePart tp;
+  if (!gauss_tile_part(sums, n_rb, n_chunks, p_max, per_part, &tp)) return;
   const uint32_t tid = threadIdx.x;
-  const uint32_t item = xcd_item(blockIdx.x, gridDim.x);
-  const uint32_t t = item / parts, part = item % parts;
-  const uint32_t c_lo = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * part / parts);
-  const uint32_t c_hi = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * (part + 1) / parts);
-  const int tx = t % gp.tiles_x, ty = t / gp.tiles_x;
+  const int tx = tp.t % gp.tiles_x, ty = tp.t / gp.tiles_x;
   const int x0 = tx * kGTile, y0 = ty * kGTile;
   for (uint32_t i = tid; i < H * H; i += kGAccBlock) {
     const int px = x0 + static_cast<int>(i % H), py = y0 + static_cast<int>(i / H);
@@ -346,10 +386,10 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_grad_tiles(
   // binned by their first tap; taps left of or above the image have none)
   auto at = [&](int row, int col) { return g[(row - y0) * H + (col - x0)]; };
   const float cx = -gp.scale[0] * gp.weight, cy = -gp.scale[1] * gp.weight;
-  const uint32_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
+  const uint32_t *row0 = tile_start + static_cast<size_t>(tp.t) * n_chunks;
   const uint32_t *row1 = row0 + n_chunks;
-  const uint32_t gsz = 1u << log2g, lane = tid & (gsz - 1u), groups = kGAccBlock >> log2g;
-  for (uint32_t c = c_lo + (tid >> log2g); c < c_hi; c += groups) {
+  const uint32_t gsz = 1u << tp.log2g, lane = tid & (gsz - 1u), groups = kGAccBlock >> tp.log2g;
+  for (uint32_t c = tp.c_lo + (tid >> tp.log2g); c < tp.c_hi; c += groups) {
     const uint32_t s = row0[c], e = row1[c];
     const uint32_t block = c / flushes, flush = c % flushes;
     for (uint32_t i = s + lane; i < e; i += gsz) {
@@ -507,26 +547,25 @@ GaussPlan gauss_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, int wi
   gp.tiles_x = (width + kGTile - 1) / kGTile;
   gp.tiles_y = (height + kGTile - 1) / kGTile;
   gp.n_tiles = static_cast<uint32_t>(gp.tiles_x) * gp.tiles_y;
+  gp.n_rb = (gp.n_chunks + 63) / 64;
   gp.records_bytes = static_cast<size_t>(gp.n_chunks) * kGCap * sizeof(float2);
   gp.table_bytes = static_cast<size_t>(gp.n_tiles + 1) * gp.n_chunks * sizeof(uint32_t);
+  gp.sums_bytes = static_cast<size_t>(gp.n_tiles + 1) * gp.n_rb * sizeof(uint32_t);
   return gp;
 }
 
-// Per-tile kernels' launch shape: lanes per run from the mean run length (one
-// record per lane), and enough workgroups per tile for eight small
-// workgroups per CU while each keeps one pass of groups.
-static void gauss_tile_shape(const GaussJob &j, uint32_t *parts_out, uint32_t *lg_out) {
-  const uint64_t runs = static_cast<uint64_t>(j.gb.n_chunks) * j.gb.n_tiles;
-  const uint64_t mean = runs ? static_cast<uint64_t>(j.ra.n_points) * (j.ra.n_iters - j.ra.burn_in) / runs : 0;
-  uint32_t lg = 0;
-  while (lg < 6 && (1ull << lg) < mean) ++lg;
-  const uint32_t groups = kGAccBlock >> lg;
-  uint32_t parts = (4 * kAccTargetGroups + j.gb.n_tiles - 1) / j.gb.n_tiles;
-  const uint32_t pmax = j.gb.n_chunks / groups > 1 ? j.gb.n_chunks / groups : 1;
-  if (parts > pmax) parts = pmax;
-  if (parts < 1) parts = 1;
-  *parts_out = parts;
-  *lg_out = lg;
+// Per-tile kernels' launch shape: p_max workgroups per tile (at most
+// kGMaxParts, fewer on images of many tiles so that the grid stays near
+// 32768 workgroups, most of which end at once), and a workgroup per
+// per_part records of the launch (all splats of the slice, an upper bound
+// on its records), so that about kGPartTarget workgroups share the work
+// whatever its spread over the tiles.
+static void gauss_tile_shape(const GaussJob &j, uint32_t *p_max_out, uint32_t *per_part_out) {
+  const uint32_t p_max = std::min<uint32_t>(kGMaxParts, std::max<uint32_t>(8u, 32768u / j.gb.n_tiles));
+  const uint64_t splats = static_cast<uint64_t>(j.ra.n_points) * (j.ra.n_iters - j.ra.burn_in);
+  const uint64_t per_part = (splats + kGPartTarget - 1) / kGPartTarget;
+  *p_max_out = p_max;
+  *per_part_out = static_cast<uint32_t>(std::max<uint64_t>(per_part, 1));
 }
 
 template <bool IDS>
@@ -541,21 +580,25 @@ static hipError_t launch_emit(const GaussJob &j, const GaussCkpt &ck, unsigned l
                        j.gb, ck, dropped);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_transpose(j.gb.chunk_start, j.gb.tile_start, j.gb.n_chunks, j.gb.n_tiles + 1, s);
+  return launch_transpose(j.gb.chunk_start, j.gb.tile_start, j.gb.n_chunks, j.gb.n_tiles + 1, s,
+                          j.gb.tile_sums);
 }
 
 hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
   if (j.ra.n_points == 0 || j.gb.n_chunks == 0) return hipSuccess;
   hipError_t e = launch_emit<false>(j, j.ck, j.dropped, s);
   if (e != hipSuccess) return e;
-  uint32_t parts, lg;
-  gauss_tile_shape(j, &parts, &lg);
+  uint32_t p_max, per_part;
+  gauss_tile_shape(j, &p_max, &per_part);
+  const dim3 grid(j.gb.n_tiles * p_max);
   if (j.gp.taps <= 6)
-    hipLaunchKernelGGL(k_splat_accumulate<6>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
-                       j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, parts, lg, j.dens);
+    hipLaunchKernelGGL(k_splat_accumulate<6>, grid, dim3(kGAccBlock), 0, s, j.gb.records,
+                       j.gb.tile_start, j.gb.tile_sums, j.gb.n_rb, j.gb.n_chunks, p_max, per_part,
+                       j.gp, j.dens);
   else
-    hipLaunchKernelGGL(k_splat_accumulate<16>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
-                       j.gb.records, j.gb.tile_start, j.gb.n_chunks, j.gp, parts, lg, j.dens);
+    hipLaunchKernelGGL(k_splat_accumulate<16>, grid, dim3(kGAccBlock), 0, s, j.gb.records,
+                       j.gb.tile_start, j.gb.tile_sums, j.gb.n_rb, j.gb.n_chunks, p_max, per_part,
+                       j.gp, j.dens);
   return hipGetLastError();
 }
 
@@ -581,16 +624,17 @@ hipError_t launch_splat_backward_slice(const GaussJob &j, uint32_t block_offset,
     const size_t words = static_cast<size_t>(j.ra.n_points) * (j.ra.n_iters - j.ra.burn_in) * 2;
     e = launch_clear_u32(reinterpret_cast<uint32_t *>(j.S), words, s);
     if (e != hipSuccess) return e;
-    uint32_t parts, lg;
-    gauss_tile_shape(j, &parts, &lg);
+    uint32_t p_max, per_part;
+    gauss_tile_shape(j, &p_max, &per_part);
+    const dim3 grid(j.gb.n_tiles * p_max);
     if (j.gp.taps <= 6)
-      hipLaunchKernelGGL(k_splat_grad_tiles<6>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
-                         j.gb.records, j.gb.ids, j.gb.tile_start, j.gb.n_chunks, j.gb.flushes,
-                         j.ra.n_points, j.gp, parts, lg, j.dLdD, j.S);
+      hipLaunchKernelGGL(k_splat_grad_tiles<6>, grid, dim3(kGAccBlock), 0, s, j.gb.records, j.gb.ids,
+                         j.gb.tile_start, j.gb.tile_sums, j.gb.n_rb, j.gb.n_chunks, p_max, per_part,
+                         j.gb.flushes, j.ra.n_points, j.gp, j.dLdD, j.S);
     else
-      hipLaunchKernelGGL(k_splat_grad_tiles<16>, dim3(j.gb.n_tiles * parts), dim3(kGAccBlock), 0, s,
-                         j.gb.records, j.gb.ids, j.gb.tile_start, j.gb.n_chunks, j.gb.flushes,
-                         j.ra.n_points, j.gp, parts, lg, j.dLdD, j.S);
+      hipLaunchKernelGGL(k_splat_grad_tiles<16>, grid, dim3(kGAccBlock), 0, s, j.gb.records,
+                         j.gb.ids, j.gb.tile_start, j.gb.tile_sums, j.gb.n_rb, j.gb.n_chunks, p_max,
+                         per_part, j.gb.flushes, j.ra.n_points, j.gp, j.dLdD, j.S);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

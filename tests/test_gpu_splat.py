@@ -172,6 +172,40 @@ def test_unequal_probabilities_8_maps(api, orc):
     assert np.linalg.norm(g.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-4
 
 
+def test_concentrated_tile_parts(api, orc):
+    # two maps contracting by 50 onto fixed points a few pixels apart: every
+    # record lands in one or two tiles, which then take the most workgroups
+    # per tile, each with an equal share of the chunks
+    A = np.array([[[0.02, 0.0], [0.0, 0.02]]] * 2, dtype=np.float32)
+    b = np.array([[0.49, 0.5], [0.5, 0.49]], dtype=np.float32)
+    system = W._system(A, b)
+    run = {"seed": 11, "instance": 0, "n_points": 1 << 16, "point_offset": 0, "n_iters": 20,
+           "burn_in": 4}
+    image = {"kind": "f32_density", "width": 256, "height": 256, "channels": 1,
+             "lo": [0, 0], "hi": [1, 1]}
+    img, ckpt = gpu_forward(api, system, run, image, 1.0, 4)
+    ref_D = orc.splat_gauss(system, run, image, 1.0)
+    got = img.data.cpu().numpy().astype(np.float64)
+    assert np.count_nonzero(ref_D) < 200
+    assert np.max(np.abs(got - ref_D)) / ref_D.max() < 2e-5
+    yy, xx = np.mgrid[0:256, 0:256]
+    G = (1.0 + xx / 256.0 + 2.0 * yy / 256.0).astype(np.float32)  # smooth: no cancellation
+    g = api.splat_backward(system, run, img, 1.0, torch.from_numpy(G).to(_dev()), ckpt, 4)
+    ref = orc.splat_gauss_backward(system, run, image, 1.0, G.astype(np.float64))
+    assert np.linalg.norm(g.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-4
+
+
+def test_density_many_tiles(api, orc):
+    # 1440 x 1440 pixels: 2025 tiles of 32 x 32, fewer workgroups per tile
+    w = W.differentiable(n_points=1 << 15, n_iters=16, burn_in=4)
+    image = dict(w["image"], width=1440, height=1440)
+    img, _ = gpu_forward(api, w["system"], w["run"], image, 1.0, 4)
+    got = img.data.cpu().numpy().astype(np.float64)
+    ref = orc.splat_gauss(w["system"], w["run"], image, 1.0)
+    assert np.max(np.abs(got - ref)) / np.max(ref) < 2e-5
+    assert abs(got.sum() - ref.sum()) / ref.sum() < 1e-5
+
+
 def test_autograd_function(api, orc):
     from paper_2606_02226_amd.autograd import cfs_splat
     w = W.differentiable(n_points=1 << 14)
