@@ -136,10 +136,11 @@ extern "C" int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_im
 namespace {
 
 // Backward workspace layout: the gradient partials of every sweep workgroup
-// of the run, then, reused by every launch slice, the slice's records, their
-// ids, the two run tables, their column sums and the splat gradients S.
+// of the run, then, reused by every launch slice, the slice's records, the
+// record index of each of its splats (pos), the two run tables, their column
+// sums and the splat gradients S (in record order).
 struct BwdLayout {
-  size_t partials, records, ids, table, sums, s, total;
+  size_t partials, records, pos, table, sums, s, total;
 };
 
 BwdLayout bwd_layout(const cfs_system *sys, const cfs_run *run, const cfs_image *img) {
@@ -151,12 +152,12 @@ BwdLayout bwd_layout(const cfs_system *sys, const cfs_run *run, const cfs_image 
     const uint32_t slice = gauss_slice(run);
     const GaussPlan p = gauss_plan(slice, run->n_iters, run->burn_in, img->width, img->height);
     l.records = align_up(p.records_bytes);
-    l.ids = align_up(static_cast<size_t>(p.n_chunks) * kGCap * sizeof(uint16_t));
+    l.pos = align_up(static_cast<size_t>(slice) * (run->n_iters - run->burn_in) * sizeof(uint32_t));
     l.table = align_up(p.table_bytes);
     l.sums = align_up(p.sums_bytes);
-    l.s = align_up(static_cast<size_t>(slice) * (run->n_iters - run->burn_in) * sizeof(float2));
+    l.s = align_up(p.records_bytes);
   }
-  l.total = l.partials + l.records + l.ids + 2 * l.table + l.sums + l.s;
+  l.total = l.partials + l.records + l.pos + 2 * l.table + l.sums + l.s;
   return l;
 }
 
@@ -199,11 +200,11 @@ extern "C" int cfs_splat_backward(const cfs_system *sys, const cfs_run *run, con
   job.partials = reinterpret_cast<float *>(ws);
   char *p = ws + l.partials;
   job.gb.records = reinterpret_cast<float2 *>(p);
-  job.gb.ids = reinterpret_cast<uint16_t *>(p + l.records);
-  job.gb.chunk_start = reinterpret_cast<uint32_t *>(p + l.records + l.ids);
-  job.gb.tile_start = reinterpret_cast<uint32_t *>(p + l.records + l.ids + l.table);
-  job.gb.tile_sums = reinterpret_cast<uint32_t *>(p + l.records + l.ids + 2 * l.table);
-  job.S = reinterpret_cast<float2 *>(p + l.records + l.ids + 2 * l.table + l.sums);
+  job.gb.pos = reinterpret_cast<uint32_t *>(p + l.records);
+  job.gb.chunk_start = reinterpret_cast<uint32_t *>(p + l.records + l.pos);
+  job.gb.tile_start = reinterpret_cast<uint32_t *>(p + l.records + l.pos + l.table);
+  job.gb.tile_sums = reinterpret_cast<uint32_t *>(p + l.records + l.pos + 2 * l.table);
+  job.S = reinterpret_cast<float2 *>(p + l.records + l.pos + 2 * l.table + l.sums);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const RunArgs ra = make_run_args(run);
   const bool splats = run->n_iters > run->burn_in;

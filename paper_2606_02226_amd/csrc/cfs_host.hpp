@@ -88,7 +88,7 @@ struct GaussJob {
   float *dens;
   unsigned long long *dropped;
   const float *dLdD;
-  float2 *S;  // backward: splat gradients [T - B][points of the slice]
+  float2 *S;  // backward: splat gradients in record order (the slice's records)
   float *partials;
   float *grad;
 };
@@ -101,7 +101,7 @@ struct GaussPlan {
 };
 GaussPlan gauss_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, int width, int height);
 hipError_t launch_splat_forward(const GaussJob &job, hipStream_t stream);
-// Backward of one launch slice: its records again (with ids), the splat
+// Backward of one launch slice: its records again (with each splat's record index), the splat
 // gradients per tile, then the adjoint sweep writing workgroup partials from
 // block_offset on; launch_grad_reduce then sums the partials of all slices.
 hipError_t launch_splat_backward_slice(const GaussJob &job, uint32_t block_offset,

@@ -139,7 +139,7 @@ struct GaussParams {
 
 struct GaussBin {
   float2 *records;       // [n_chunks][kGCap] pixel coordinates, runs by tile
-  uint16_t *ids;         // backward only: each record's slot before sorting (or null)
+  uint32_t *pos;         // backward only: [T - B][points] each splat's record index, or ~0u
   uint32_t *chunk_start; // [n_chunks][n_tiles + 1] as the chunks write them
   uint32_t *tile_start;  // [n_tiles + 1][n_chunks] transposed for the accumulate
   uint32_t *tile_sums;   // [n_tiles + 1][n_rb]: column sums of 64-chunk blocks (record totals)

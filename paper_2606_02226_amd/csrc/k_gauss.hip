@@ -84,12 +84,13 @@ __device__ uint32_t gblock_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsu
   return total;
 }
 
-// IDS: also write, per record, its slot in the stage before sorting
-// (slot * kGBlock + lane), from which the adjoint recovers the point and the
-// iteration of every record.
-template <bool IDS>
-__device__ void gauss_flush(float2 *stage, uint16_t *idstage, uint32_t *cnt, uint32_t *wsum, int used,
-                            uint32_t chunk, const GaussParams &gp, const GaussBin &gb) {
+// POS: also write, for every splat of the flush (points of the launch slice
+// only), the index of its record, or kGInvalid for a splat off the image, at
+// pos[iteration - B - 1][point]: the adjoint reads each splat's gradient
+// there after the per-tile kernel has written it in record order.
+template <bool POS>
+__device__ void gauss_flush(float2 *stage, uint32_t *cnt, uint32_t *wsum, int used, uint32_t chunk,
+                            uint32_t points, const GaussParams &gp, const GaussBin &gb) {
   __syncthreads();
   const int tid = threadIdx.x;
   float2 e[kGSlots];
@@ -105,30 +106,34 @@ __device__ void gauss_flush(float2 *stage, uint16_t *idstage, uint32_t *cnt, uin
   const uint32_t base = chunk * kGCap;
   uint32_t *row = gb.chunk_start + static_cast<size_t>(chunk) * (gb.n_tiles + 1);
   for (uint32_t t = tid; t <= gb.n_tiles; t += kGBlock) row[t] = base + (t < gb.n_tiles ? cnt[t] : total);
+  if constexpr (POS) {
+    const uint32_t f = chunk % gb.flushes;
+    const uint32_t n = (chunk / gb.flushes) * kGBlock + tid;
+    if (n < points) {
+#pragma unroll
+      for (int i = 0; i < kGSlots; ++i)
+        if (i < used)
+          gb.pos[static_cast<size_t>(f * kGSlots + i) * points + n] =
+              tl[i] != kGInvalid ? base + cnt[tl[i]] + r[i] : kGInvalid;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < kGSlots; ++i)
-    if (tl[i] != kGInvalid) {
-      stage[cnt[tl[i]] + r[i]] = e[i];
-      if constexpr (IDS) idstage[cnt[tl[i]] + r[i]] = static_cast<uint16_t>(i * kGBlock + tid);
-    }
+    if (tl[i] != kGInvalid) stage[cnt[tl[i]] + r[i]] = e[i];
   __syncthreads();
-  for (uint32_t i = tid; i < total; i += kGBlock) {
-    gb.records[static_cast<size_t>(base) + i] = stage[i];
-    if constexpr (IDS) gb.ids[static_cast<size_t>(base) + i] = idstage[i];
-  }
+  for (uint32_t i = tid; i < total; i += kGBlock) gb.records[static_cast<size_t>(base) + i] = stage[i];
   __syncthreads();
   for (uint32_t t = tid; t < gb.n_tiles; t += kGBlock) cnt[t] = 0u;
   __syncthreads();
 }
 
-template <bool EQUAL, bool IDS>
+template <bool EQUAL, bool POS>
 __global__ __launch_bounds__(kGBlock) void k_splat_emit(MapTable<2> mt, RunArgs ra, GaussParams gp,
                                                         GaussBin gb, GaussCkpt ck,
                                                         unsigned long long *dropped_out) {
   __shared__ float table[kMaxMaps * 8];
   __shared__ uint32_t th[kThWords];
   __shared__ float2 stage[kGCap];
-  __shared__ uint16_t idstage[IDS ? kGCap : 1];
   __shared__ uint32_t cnt[kGMaxTiles];
   __shared__ uint32_t wsum[kGWaves + 1];
   const int tid = threadIdx.x;
@@ -179,14 +184,14 @@ __global__ __launch_bounds__(kGBlock) void k_splat_emit(MapTable<2> mt, RunArgs 
         }
         stage[slot * kGBlock + tid] = rec;
         if (++slot == kGSlots) {
-          gauss_flush<IDS>(stage, idstage, cnt, wsum, slot, chunk, gp, gb);
+          gauss_flush<POS>(stage, cnt, wsum, slot, chunk, ra.n_points, gp, gb);
           slot = 0;
           ++chunk;
         }
       }
     }
   }
-  if (slot > 0) gauss_flush<IDS>(stage, idstage, cnt, wsum, slot, chunk, gp, gb);
+  if (slot > 0) gauss_flush<POS>(stage, cnt, wsum, slot, chunk, ra.n_points, gp, gb);
   if (active && dropped_out && dropped)
     __hip_atomic_fetch_add(dropped_out, static_cast<unsigned long long>(dropped), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -361,14 +366,14 @@ __device__ __forceinline__ void splat_grad_px(float x, float y, const GaussParam
 // Per record of one tile and chunk range: the gradient of the loss with
 // respect to the splatted position, from an LDS copy of the tile's upstream
 // gradient with the same halo as the forward accumulate, written to
-// S[iteration - B - 1][point] (points of the launch slice).  Workgroups,
-// tile parts and lane groups as in the forward accumulate.
+// S at the record's own index (coalesced; the adjoint finds it through the
+// emit's pos map).  Workgroups, tile parts and lane groups as in the forward
+// accumulate.
 template <int TAPS>
 __global__ __launch_bounds__(kGAccBlock) void k_splat_grad_tiles(
-    const float2 *__restrict__ rec, const uint16_t *__restrict__ ids,
-    const uint32_t *__restrict__ tile_start, const uint32_t *__restrict__ sums, uint32_t n_rb,
-    uint32_t n_chunks, uint32_t p_max, uint32_t per_part, uint32_t flushes, uint32_t points,
-    GaussParams gp,
+    const float2 *__restrict__ rec, const uint32_t *__restrict__ tile_start,
+    const uint32_t *__restrict__ sums, uint32_t n_rb, uint32_t n_chunks, uint32_t p_max,
+    uint32_t per_part, GaussParams gp,
     const float *__restrict__ G, float2 *__restrict__ S) {
   constexpr int H = kGTile + TAPS - 1;
   __shared__ float g[H * H];
@@ -391,23 +396,21 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_grad_tiles(
   const uint32_t gsz = 1u << tp.log2g, lane = tid & (gsz - 1u), groups = kGAccBlock >> tp.log2g;
   for (uint32_t c = tp.c_lo + (tid >> tp.log2g); c < tp.c_hi; c += groups) {
     const uint32_t s = row0[c], e = row1[c];
-    const uint32_t block = c / flushes, flush = c % flushes;
     for (uint32_t i = s + lane; i < e; i += gsz) {
       const float2 r = rec[i];
-      const uint32_t slot = ids[i];
-      const uint32_t n = block * kGBlock + slot % kGBlock;
-      const uint32_t tt = flush * kGSlots + slot / kGBlock;
       float ax, ay;
       splat_grad_px<TAPS>(r.x, r.y, gp, at, &ax, &ay);
-      S[static_cast<size_t>(tt) * points + n] = make_float2(ax * cx, ay * cy);
+      S[i] = make_float2(ax * cx, ay * cy);
     }
   }
 }
 
 // The adjoint sweep of each point of a launch slice, with the splat
-// gradients S[t - B - 1][point] already computed per tile.
+// gradients already computed per tile: splat t of point n has its gradient
+// at S[pos[t - B - 1][n]] (none if pos holds kGInvalid: off the image).
 template <int NG, bool EQUAL>
 __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, RunArgs ra,
+                                                               const uint32_t *__restrict__ pos,
                                                                const float2 *__restrict__ S,
                                                                GaussCkpt ck, float *partials,
                                                                uint32_t block_offset) {
@@ -468,9 +471,12 @@ __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, R
         const uint32_t t = t_start + m;
         float s0 = 0.0f, s1 = 0.0f;
         if (t > B) {
-          const float2 sv = S[static_cast<size_t>(t - B - 1) * ra.n_points + n];
-          s0 = sv.x;
-          s1 = sv.y;
+          const uint32_t q = pos[static_cast<size_t>(t - B - 1) * ra.n_points + n];
+          if (q != kGInvalid) {
+            const float2 sv = S[q];
+            s0 = sv.x;
+            s1 = sv.y;
+          }
         }
         float c0 = 0.0f, c1 = 0.0f;
         if (k_next >= 0) {
@@ -568,15 +574,15 @@ static void gauss_tile_shape(const GaussJob &j, uint32_t *p_max_out, uint32_t *p
   *per_part_out = static_cast<uint32_t>(std::max<uint64_t>(per_part, 1));
 }
 
-template <bool IDS>
+template <bool POS>
 static hipError_t launch_emit(const GaussJob &j, const GaussCkpt &ck, unsigned long long *dropped,
                               hipStream_t s) {
   const uint32_t blocks = (j.ra.n_points + kGBlock - 1) / kGBlock;
   if (j.equal)
-    hipLaunchKernelGGL((k_splat_emit<true, IDS>), dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp,
+    hipLaunchKernelGGL((k_splat_emit<true, POS>), dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp,
                        j.gb, ck, dropped);
   else
-    hipLaunchKernelGGL((k_splat_emit<false, IDS>), dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp,
+    hipLaunchKernelGGL((k_splat_emit<false, POS>), dim3(blocks), dim3(kGBlock), 0, s, j.mt, j.ra, j.gp,
                        j.gb, ck, dropped);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -607,34 +613,32 @@ static void launch_sweep(const GaussJob &j, uint32_t block_offset, hipStream_t s
   const uint32_t blocks = (j.ra.n_points + kGBwdBlock - 1) / kGBwdBlock;
   if (j.equal)
     hipLaunchKernelGGL((k_splat_backward<NG, true>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt, j.ra,
-                       j.S, j.ck, j.partials, block_offset);
+                       j.gb.pos, j.S, j.ck, j.partials, block_offset);
   else
     hipLaunchKernelGGL((k_splat_backward<NG, false>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt, j.ra,
-                       j.S, j.ck, j.partials, block_offset);
+                       j.gb.pos, j.S, j.ck, j.partials, block_offset);
 }
 
 hipError_t launch_splat_backward_slice(const GaussJob &j, uint32_t block_offset, hipStream_t s) {
   if (j.ra.n_points == 0) return hipSuccess;
   hipError_t e = hipSuccess;
   if (j.gb.n_chunks) {
-    // the slice's records again, with their ids, then the splat gradients per tile
+    // the slice's records again with the record index of every splat, then
+    // the splat gradients per tile, in record order
     const GaussCkpt none{nullptr, 1, 0};
     e = launch_emit<true>(j, none, nullptr, s);
-    if (e != hipSuccess) return e;
-    const size_t words = static_cast<size_t>(j.ra.n_points) * (j.ra.n_iters - j.ra.burn_in) * 2;
-    e = launch_clear_u32(reinterpret_cast<uint32_t *>(j.S), words, s);
     if (e != hipSuccess) return e;
     uint32_t p_max, per_part;
     gauss_tile_shape(j, &p_max, &per_part);
     const dim3 grid(j.gb.n_tiles * p_max);
     if (j.gp.taps <= 6)
-      hipLaunchKernelGGL(k_splat_grad_tiles<6>, grid, dim3(kGAccBlock), 0, s, j.gb.records, j.gb.ids,
+      hipLaunchKernelGGL(k_splat_grad_tiles<6>, grid, dim3(kGAccBlock), 0, s, j.gb.records,
                          j.gb.tile_start, j.gb.tile_sums, j.gb.n_rb, j.gb.n_chunks, p_max, per_part,
-                         j.gb.flushes, j.ra.n_points, j.gp, j.dLdD, j.S);
+                         j.gp, j.dLdD, j.S);
     else
       hipLaunchKernelGGL(k_splat_grad_tiles<16>, grid, dim3(kGAccBlock), 0, s, j.gb.records,
-                         j.gb.ids, j.gb.tile_start, j.gb.tile_sums, j.gb.n_rb, j.gb.n_chunks, p_max,
-                         per_part, j.gb.flushes, j.ra.n_points, j.gp, j.dLdD, j.S);
+                         j.gb.tile_start, j.gb.tile_sums, j.gb.n_rb, j.gb.n_chunks, p_max, per_part,
+                         j.gp, j.dLdD, j.S);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
