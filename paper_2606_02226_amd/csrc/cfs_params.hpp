@@ -122,9 +122,11 @@ constexpr int kGMaxTiles = 2048;
 constexpr int kGAccBlock = 256;
 // Per-tile Gaussian kernels: at most this many workgroups per tile, each
 // taking an equal share of the chunks; a tile uses as many of them as its
-// record total asks for at kGPartTarget workgroups for the whole launch.
+// record total asks for at one workgroup per 1/kGPartTarget of the launch's
+// splats (small workgroups: the dense tiles' parts then balance over the
+// chip; 4096 and 16384 measured slower).
 constexpr uint32_t kGMaxParts = 64;
-constexpr uint32_t kGPartTarget = 4096;
+constexpr uint32_t kGPartTarget = 32768;
 constexpr int kGBwdBlock = 256;
 constexpr int kMaxSeg = 16;  // longest checkpoint segment
 

@@ -563,9 +563,9 @@ GaussPlan gauss_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, int wi
 // Per-tile kernels' launch shape: p_max workgroups per tile (at most
 // kGMaxParts, fewer on images of many tiles so that the grid stays near
 // 32768 workgroups, most of which end at once), and a workgroup per
-// per_part records of the launch (all splats of the slice, an upper bound
-// on its records), so that about kGPartTarget workgroups share the work
-// whatever its spread over the tiles.
+// per_part records, per_part being the launch's splats (an upper bound on
+// its records) over kGPartTarget, so that dense tiles take many small
+// workgroups whatever the spread of the work over the tiles.
 static void gauss_tile_shape(const GaussJob &j, uint32_t *p_max_out, uint32_t *per_part_out) {
   const uint32_t p_max = std::min<uint32_t>(kGMaxParts, std::max<uint32_t>(8u, 32768u / j.gb.n_tiles));
   const uint64_t splats = static_cast<uint64_t>(j.ra.n_points) * (j.ra.n_iters - j.ra.burn_in);
