@@ -322,8 +322,9 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
 // ---------------------------------------------------------------------------
 // dL/dx, dL/dy (in pixels, before the chain to positions) of one splat at
 // pixel coordinates (x, y): the taps' weights g and derivatives dg against
-// the upstream gradient G, read through `at(row, col)` for the taps that
-// have a weight or a derivative.
+// the upstream gradient G, read through `at(row, col)` for every candidate
+// tap (those without a weight or a derivative add exact zeros, so the sums
+// are those over the taps that have one; `at` must accept every candidate).
 template <int TAPS, typename GAt>
 __device__ __forceinline__ void splat_grad_px(float x, float y, const GaussParams &gp, GAt at,
                                               float *ax_out, float *ay_out) {
@@ -347,11 +348,9 @@ __device__ __forceinline__ void splat_grad_px(float x, float y, const GaussParam
   float ax = 0.0f, ay = 0.0f;
 #pragma unroll
   for (int b = 0; b < TAPS; ++b) {
-    if (gy[b] == 0.0f && dgy[b] == 0.0f) continue;
     float sg = 0.0f, sdg = 0.0f;
 #pragma unroll
     for (int a = 0; a < TAPS; ++a) {
-      if (gx[a] == 0.0f && dgx[a] == 0.0f) continue;
       const float v = at(j0 + b, i0 + a);
       sg += v * gx[a];
       sdg += v * dgx[a];
@@ -365,7 +364,8 @@ __device__ __forceinline__ void splat_grad_px(float x, float y, const GaussParam
 
 // Per record of one tile and chunk range: the gradient of the loss with
 // respect to the splatted position, from an LDS copy of the tile's upstream
-// gradient with the same halo as the forward accumulate, written to
+// gradient with the same halo and margins as the forward accumulate (the
+// margin left of and above the tile holds zeros), written to
 // S at the record's own index (coalesced; the adjoint finds it through the
 // emit's pos map).  Workgroups, tile parts and lane groups as in the forward
 // accumulate.
@@ -376,20 +376,26 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_grad_tiles(
     uint32_t per_part, GaussParams gp,
     const float *__restrict__ G, float2 *__restrict__ S) {
   constexpr int H = kGTile + TAPS - 1;
-  __shared__ float g[H * H];
+  constexpr int M = TAPS - 1;
+  constexpr int HM = H + M;
+  __shared__ float g[HM * HM];
   TilePart tp;
   if (!gauss_tile_part(sums, n_rb, n_chunks, p_max, per_part, &tp)) return;
   const uint32_t tid = threadIdx.x;
   const int tx = tp.t % gp.tiles_x, ty = tp.t / gp.tiles_x;
   const int x0 = tx * kGTile, y0 = ty * kGTile;
-  for (uint32_t i = tid; i < H * H; i += kGAccBlock) {
-    const int px = x0 + static_cast<int>(i % H), py = y0 + static_cast<int>(i / H);
-    g[i] = (px < gp.width && py < gp.height) ? G[static_cast<size_t>(py) * gp.width + px] : 0.0f;
+  for (uint32_t i = tid; i < HM * HM; i += kGAccBlock) {
+    const int ox = static_cast<int>(i % HM) - M, oy = static_cast<int>(i / HM) - M;
+    const int px = x0 + ox, py = y0 + oy;
+    g[i] = (ox >= 0 && oy >= 0 && px < gp.width && py < gp.height)
+               ? G[static_cast<size_t>(py) * gp.width + px]
+               : 0.0f;
   }
   __syncthreads();
-  // every tap with a weight lies in [x0, x0 + H) x [y0, y0 + H) (records are
-  // binned by their first tap; taps left of or above the image have none)
-  auto at = [&](int row, int col) { return g[(row - y0) * H + (col - x0)]; };
+  // every candidate tap lies in [x0 - M, x0 + H) x [y0 - M, y0 + H) (records
+  // are binned by their first tap; taps left of or above the tile are off the
+  // image and read the zero margin)
+  auto at = [&](int row, int col) { return g[(row - y0 + M) * HM + (col - x0 + M)]; };
   const float cx = -gp.scale[0] * gp.weight, cy = -gp.scale[1] * gp.weight;
   const uint32_t *row0 = tile_start + static_cast<size_t>(tp.t) * n_chunks;
   const uint32_t *row1 = row0 + n_chunks;
