@@ -105,8 +105,12 @@ enum { CFS_PREC_F32 = 0, CFS_PREC_F64 = 1 };
  * in LDS and writes them out as per-tile runs; a second kernel accumulates
  * every tile in LDS and merges it into the image (needs workspace; count
  * images of at most 2^25 elements, depth images of at most 2^24 pixels).
- * AUTO picks BINNED for large runs that qualify.  Both give bit-identical
- * images (integer sums and minima do not depend on order). */
+ * One workgroup's records must fit one launch's record budget (1 GiB), which
+ * holds about 10^6 splatted steps per point (count images) or 1.4 x 10^5
+ * (depth images); longer runs take DIRECT under AUTO and are refused
+ * (CFS_E_UNSUPPORTED) under BINNED.  AUTO picks BINNED for large runs that
+ * qualify.  Both give bit-identical images (integer sums and minima do not
+ * depend on order). */
 enum { CFS_SPLAT_AUTO = 0, CFS_SPLAT_DIRECT = 1, CFS_SPLAT_BINNED = 2 };
 
 /* How the composed transform meets the iteration (Section 3, fig. "circle"
@@ -174,7 +178,9 @@ typedef struct cfs_image {
   int32_t width, height;  /* 1 .. 65536 each; W*H*channels <= 2^31 */
   int32_t channels;       /* 1, or n_maps for per-index counts */
   float lo[2], hi[2];     /* window, lo < hi */
-  float near_plane;       /* depth images: splats with depth <= near dropped */
+  float near_plane;       /* depth images: splats with depth <= near dropped;
+                             must be >= 0 (keys order depths by their FP32
+                             bits, which is their order only when >= 0) */
   void *data;             /* device, element type per kind (see above) */
   uint32_t *density;      /* device uint32 [H][W], CFS_IMAGE_U64_DEPTH only */
   unsigned long long *dropped; /* device counter of dropped splats, or NULL */
@@ -295,7 +301,8 @@ int cfs_chaos_scene(const cfs_system *sys, const cfs_object *objects, int32_t n_
  * to rounding.
  *   ckpt: device, nullable; float [ceil(n_iters / ckpt_every)][n_points][2]:
  *     positions at iterations 0, c, 2c, ... (c = ckpt_every in 1..16), from
- *     which cfs_splat_backward recomputes its segments.
+ *     which cfs_splat_backward recomputes its segments (written also when
+ *     burn_in == n_iters, where nothing is splatted).
  *   workspace: device, cfs_splat_workspace() bytes, 256-byte aligned.
  * sigma_px in (0, 2.5]. */
 int cfs_splat(const cfs_system *sys, const cfs_run *run, const cfs_image *img,
@@ -322,7 +329,8 @@ size_t cfs_splat_backward_workspace(const cfs_system *sys, const cfs_run *run,
  * dL/dD over the splats' records (recomputed from the random streams), then
  * each point's sweep reads them.  workspace: device,
  * cfs_splat_backward_workspace() bytes, 256-byte aligned.
- * Systems of at most 8 maps. */
+ * With burn_in == n_iters (no splats) or no points the gradient is exactly
+ * zero and nothing else is read.  Systems of at most 8 maps. */
 int cfs_splat_backward(const cfs_system *sys, const cfs_run *run,
                        const cfs_image *img, float sigma_px,
                        const float *dL_dD, const float *ckpt,
@@ -412,6 +420,37 @@ int cfs_autotune(const cfs_batch_item *items, int32_t n_items, cfs_plan *out,
  * ctrs, out: device uint32 [n][4]. */
 int cfs_philox_dump(uint64_t seed, const uint32_t *ctrs, uint32_t *out,
                     uint64_t n, void *stream);
+
+/* Ceiling probes for the rooflines (measurement hook).  The splat is an
+ * atomic histogram (Section 1; Section 4 names its atomics as a limit), and
+ * the chip's atomic rates are not published, so they are measured with the
+ * operation types of the splats:
+ *   COPY         buf = [src half | dst half]: copy bytes / 2; *done = bytes
+ *                moved (read + written);
+ *   DEV_ADD_U32  about `ops` u32 atomic adds at uniformly random elements of
+ *                the device working set buf (bytes / 4 elements);
+ *   DEV_MIN_U64  the same with u64 atomic minima (bytes / 8 elements);
+ *   LDS_ADD_U32  about `ops` u32 atomic adds at random words of a 64 KiB LDS
+ *                table per 1024-lane workgroup (512 workgroups); buf
+ *                receives one word per workgroup (bytes >= 2 KiB);
+ *   LDS_MIN_U64  the same with u64 atomic minima (bytes >= 4 KiB);
+ *   LDS_ADD_U64  the same with u64 atomic adds (bytes >= 4 KiB);
+ *   PHILOX       about `ops` Philox4x32-10 blocks (buf >= 4 MiB receives one
+ *                word per lane).
+ * buf: device, 16-byte aligned, caller-owned; its contents are overwritten.
+ * *done (host) receives the operations (or bytes) actually issued; the
+ * caller times the call with events on `stream`.  Enqueues one kernel. */
+enum {
+  CFS_MB_COPY = 0,
+  CFS_MB_DEV_ADD_U32 = 1,
+  CFS_MB_DEV_MIN_U64 = 2,
+  CFS_MB_LDS_ADD_U32 = 3,
+  CFS_MB_LDS_MIN_U64 = 4,
+  CFS_MB_PHILOX = 5,
+  CFS_MB_LDS_ADD_U64 = 6
+};
+int cfs_microbench(int32_t kind, void *buf, size_t bytes, uint64_t ops,
+                   uint64_t *done, void *stream);
 
 #ifdef __cplusplus
 }

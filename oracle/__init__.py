@@ -363,3 +363,97 @@ def gauss_loss(system, run, image, sigma_px, target):
     """L = sum (D - D*)^2 with D from splat_gauss."""
     D = splat_gauss(system, run, image, sigma_px)
     return float(np.sum((D - target) ** 2)), D
+
+
+# --------------------------------------------------------------------------
+# Point-range shards of the whole workload (test infrastructure).
+#
+# Points are independent and every point's random stream is keyed by its
+# global id, so the image of a run is the sum (counts, densities) or the
+# minimum (depth keys) of the images of any partition of its points into
+# ranges (Section 1: each point colours its own pixels).  The helpers below
+# run the single-threaded oracle on equal point ranges in threads (ctypes
+# releases the interpreter lock during each call) and combine the parts by
+# that definition; no arithmetic of the method is done here.
+# --------------------------------------------------------------------------
+
+def host_threads(cap=16):
+    """Threads for the sharded oracle: the cores this process may run on,
+    at most ``cap`` (a GPU machine grants one GPU's share of its cores)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, cap))
+
+
+def _ranges(run, parts):
+    n = int(run["n_points"])
+    off = int(run.get("point_offset", 0))
+    parts = max(1, min(parts, n)) if n else 1
+    b = [n * i // parts for i in range(parts + 1)]
+    return [dict(run, n_points=b[i + 1] - b[i], point_offset=off + b[i])
+            for i in range(parts) if b[i + 1] > b[i]]
+
+
+def _pool_map(fn, items, threads):
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        return list(ex.map(fn, items))
+
+
+def chaos_count_sharded(system, run, image, threads=None):
+    """chaos_count of the whole run as the sum of its point-range parts:
+    {'image', 'dropped'} (image uint32, as chaos_count returns it)."""
+    threads = threads or host_threads()
+    runs = _ranges(run, threads)
+    if not runs:
+        return chaos_count(system, run, image)
+    parts = _pool_map(lambda r: chaos_count(system, r, image), runs, threads)
+    total = parts[0]["image"].astype(np.uint64)
+    for p in parts[1:]:
+        total += p["image"]
+    assert int(total.max(initial=0)) < 2**32
+    return {"image": total.astype(np.uint32), "dropped": sum(p["dropped"] for p in parts)}
+
+
+def chaos_depth_sharded(system, run, image, near, threads=None):
+    """chaos_depth of the whole run: key image the minimum and density the
+    sum of the point-range parts: {'depth', 'density', 'dropped'}."""
+    threads = threads or host_threads()
+    runs = _ranges(run, threads)
+    if not runs:
+        return chaos_depth(system, run, image, near)
+    parts = _pool_map(lambda r: chaos_depth(system, r, image, near), runs, threads)
+    depth = parts[0]["depth"]
+    dens = parts[0]["density"].astype(np.uint64)
+    for p in parts[1:]:
+        np.minimum(depth, p["depth"], out=depth)
+        dens += p["density"]
+    return {"depth": depth, "density": dens.astype(np.uint32),
+            "dropped": sum(p["dropped"] for p in parts)}
+
+
+def splat_gauss_sharded(system, run, image, sigma_px, threads=None):
+    """splat_gauss of the whole run: each part is normalised by its own
+    point count, so the whole density is the parts weighted by their share
+    of the points."""
+    threads = threads or host_threads()
+    N = int(run["n_points"])
+    runs = _ranges(run, threads)
+    parts = _pool_map(lambda r: (r["n_points"], splat_gauss(system, r, image, sigma_px)),
+                      runs, threads)
+    return sum(d * (n / N) for n, d in parts)
+
+
+def splat_gauss_backward_sharded(system, run, image, sigma_px, dL_dD, threads=None):
+    """splat_gauss_backward of the whole run for a fixed upstream gradient:
+    the gradient is a sum over points, each part normalised by its own point
+    count, so the parts are weighted by their share of the points."""
+    threads = threads or host_threads()
+    N = int(run["n_points"])
+    runs = _ranges(run, threads)
+    parts = _pool_map(lambda r: (r["n_points"],
+                                 splat_gauss_backward(system, r, image, sigma_px, dL_dD)),
+                      runs, threads)
+    return sum(g * (n / N) for n, g in parts)

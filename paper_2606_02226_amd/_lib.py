@@ -33,8 +33,10 @@ EXPORTS = (
     "cfs_splat_backward", "cfs_batch_create", "cfs_batch_run", "cfs_batch_update",
     "cfs_batch_plan", "cfs_batch_destroy", "cfs_autotune", "cfs_philox_dump",
     "cfs_chaos_scene_workspace", "cfs_chaos_scene", "cfs_l2_loss_workspace", "cfs_l2_loss",
-    "cfs_timing_enable", "cfs_timing_read",
+    "cfs_timing_enable", "cfs_timing_read", "cfs_microbench",
 )
+MICROBENCH = {"copy": 0, "dev_add_u32": 1, "dev_min_u64": 2, "lds_add_u32": 3,
+              "lds_min_u64": 4, "philox": 5, "lds_add_u64": 6}
 
 
 class CfsSystem(C.Structure):
@@ -126,6 +128,8 @@ def load():
     lib.cfs_philox_dump.argtypes = [C.c_uint64, P, P, C.c_uint64, P]
     lib.cfs_timing_enable.argtypes = [C.c_int32]
     lib.cfs_timing_read.argtypes = [P, C.c_int32, P]
+    lib.cfs_microbench.argtypes = [C.c_int32, P, C.c_size_t, C.c_uint64,
+                                   C.POINTER(C.c_uint64), P]
     lib.cfs_l2_loss_workspace.argtypes = [C.c_uint64]
     lib.cfs_l2_loss_workspace.restype = C.c_size_t
     lib.cfs_l2_loss.argtypes = [P, P, C.c_uint64, P, P, P, C.c_size_t, P]

@@ -30,6 +30,19 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _scratch(nbytes, device, stream=None, dtype=torch.uint8):
+    """A workspace tensor allocated here for one call.  Torch's caching
+    allocator ties a block to the stream it was allocated on and may hand it
+    out again as soon as this function's reference is dropped; when the
+    kernels run on another stream, record that stream on the tensor so the
+    block is not reused before the work queued there has finished."""
+    elem = torch.empty((), dtype=dtype).element_size()
+    t = torch.empty(max((int(nbytes) + elem - 1) // elem, 1), dtype=dtype, device=device)
+    if stream is not None:
+        t.record_stream(stream)
+    return t
+
+
 class System:
     """C view of a system dict; keeps the host arrays alive."""
 
@@ -148,12 +161,25 @@ def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
         if workspace is not None and workspace.numel() >= ws_bytes:
             ws = workspace
         else:
-            ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device=image.data.device)
+            ws = _scratch(ws_bytes, image.data.device, stream)
     rc = lib.cfs_chaos_game(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
                             _ptr(final), _ptr(last), _ptr(indices), _ptr(ws),
                             C.c_size_t(ws_bytes), _stream_handle(stream))
     check(rc, "cfs_chaos_game")
     return image
+
+
+def microbench(kind, buf, ops=0, stream=None):
+    """Enqueue one ceiling probe (cfs_microbench) over the uint8 device
+    tensor ``buf``; returns the operations (bytes for 'copy') it issues.
+    ``kind``: copy, dev_add_u32, dev_min_u64, lds_add_u32, lds_min_u64,
+    philox."""
+    done = C.c_uint64(0)
+    check(_lib.load().cfs_microbench(_lib.MICROBENCH[kind], _ptr(buf),
+                                     C.c_size_t(buf.numel() * buf.element_size()),
+                                     C.c_uint64(int(ops)), C.byref(done),
+                                     _stream_handle(stream)), "cfs_microbench")
+    return int(done.value)
 
 
 def timing_enable(on=True):
@@ -217,7 +243,7 @@ def chaos_scene(system, objects, run, image, *, precision="f32", splat_path="aut
         if workspace is not None and workspace.numel() >= ws_bytes:
             ws = workspace
         else:
-            ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device=image.data.device)
+            ws = _scratch(ws_bytes, image.data.device, stream)
     rc = lib.cfs_chaos_scene(C.byref(sysc.struct), objs, len(objects), C.byref(runc),
                              C.byref(image.struct), _ptr(ws), C.c_size_t(ws_bytes),
                              _stream_handle(stream))
@@ -265,7 +291,7 @@ def splat(system, run, image, sigma_px, *, ckpt=None, ckpt_every=8, workspace=No
                                        C.byref(image.struct), C.c_float(sigma_px)))
     ws = workspace
     if need and (ws is None or ws.numel() < need):
-        ws = torch.empty(need, dtype=torch.uint8, device=image.data.device)
+        ws = _scratch(need, image.data.device, stream)
     rc = lib.cfs_splat(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
                        C.c_float(sigma_px), _ptr(ckpt), C.c_int32(int(ckpt_every)),
                        _ptr(ws if need else None), C.c_size_t(need), _stream_handle(stream))
@@ -286,10 +312,14 @@ def splat_backward(system, run, image, sigma_px, dL_dD, ckpt, ckpt_every=8, grad
     if workspace is not None and workspace.numel() >= need:
         ws = workspace
     else:
-        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        ws = _scratch(need, dev, stream)
     if grad is None:
         grad = torch.empty((sysc.n_maps, 6), dtype=torch.float32, device=dev)
+        if stream is not None:
+            grad.record_stream(stream)
     g = dL_dD.contiguous()
+    if stream is not None and g.data_ptr() != dL_dD.data_ptr():
+        g.record_stream(stream)
     rc = lib.cfs_splat_backward(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
                                 C.c_float(sigma_px), _ptr(g), _ptr(ckpt),
                                 C.c_int32(int(ckpt_every)), _ptr(grad), _ptr(ws),
@@ -309,12 +339,21 @@ def l2_loss(density, target, *, grad=None, want_grad=True, workspace=None, strea
     if d.dtype != torch.float32 or t.dtype != torch.float32 or d.numel() != t.numel():
         raise ValueError("density and target must be float32 tensors of equal size")
     n = d.numel()
+    if stream is not None:
+        # copies made by .contiguous() above are read on ``stream``
+        for src, cp in ((density, d), (target, t)):
+            if cp.data_ptr() != src.data_ptr():
+                cp.record_stream(stream)
     if grad is None and want_grad:
         grad = torch.empty_like(d)
+        if stream is not None:
+            grad.record_stream(stream)
     loss = torch.empty(1, dtype=torch.float64, device=d.device)
+    if stream is not None:
+        loss.record_stream(stream)
     ws_bytes = int(lib.cfs_l2_loss_workspace(C.c_uint64(n)))
     if workspace is None or workspace.numel() * workspace.element_size() < ws_bytes:
-        workspace = torch.empty((ws_bytes + 7) // 8, dtype=torch.float64, device=d.device)
+        workspace = _scratch(ws_bytes, d.device, stream, dtype=torch.float64)
     check(lib.cfs_l2_loss(_ptr(d), _ptr(t), C.c_uint64(n), _ptr(grad), _ptr(loss),
                           _ptr(workspace), C.c_size_t(ws_bytes), _stream_handle(stream)),
           "cfs_l2_loss")

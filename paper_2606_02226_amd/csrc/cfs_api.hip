@@ -262,15 +262,30 @@ extern "C" int cfs_image_clear(const cfs_image *img, void *stream) {
 
 namespace {
 
-// Points per launch of the binned path: at most 2^24, and few enough that the
-// records of one launch take at most 1 GiB (2^29 16-bit or 2^27 8-byte
-// records), which also keeps record indices within 31 bits.
-uint32_t binned_slice(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
+// Records of one launch of the binned path: at most 1 GiB (2^29 16-bit or
+// 2^27 8-byte records), which keeps record indices within 31 bits and chunk
+// indices within 24 (the kernels index records in 32-bit arithmetic).
+uint64_t binned_record_budget(bool depth) { return depth ? (1ull << 27) : (1ull << 29); }
+
+uint64_t binned_block_records(const cfs_run *run, bool depth, uint32_t per_iter) {
   const uint64_t slots = depth ? kDSlots : kBinSlots;
   const uint64_t cap = depth ? kDCap : kChunkCap;
   const uint64_t flushes =
       (static_cast<uint64_t>(run->n_iters - run->burn_in) * per_iter + slots - 1) / slots;
-  uint64_t max_blocks = (depth ? (1ull << 27) : (1ull << 29)) / (flushes * cap);
+  return flushes * cap;
+}
+
+// Whether one workgroup's records fit the budget of a launch (runs of more
+// than about 10^6 splats per point do not, and take the direct splat).
+bool binned_fits(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
+  return binned_block_records(run, depth, per_iter) <= binned_record_budget(depth);
+}
+
+// Points per launch of the binned path: at most 2^24, and few enough that the
+// records of one launch stay within binned_record_budget() (the caller has
+// checked binned_fits(), so one workgroup's records always do).
+uint32_t binned_slice(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
+  uint64_t max_blocks = binned_record_budget(depth) / binned_block_records(run, depth, per_iter);
   if (max_blocks < 1) max_blocks = 1;
   uint64_t pts = max_blocks * kBinBlock;
   if (pts > (1ull << 24)) pts = 1ull << 24;
@@ -284,8 +299,10 @@ bool use_binned(const cfs_run *run, const cfs_image *img) {
   if (img->kind != CFS_IMAGE_U32_COUNT && img->kind != CFS_IMAGE_U64_DEPTH) return false;
   if (run->n_iters == run->burn_in || run->n_points == 0) return false;
   const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
-  const uint64_t tile = img->kind == CFS_IMAGE_U64_DEPTH ? kDTileElems : kTileElems;
+  const bool depth = img->kind == CFS_IMAGE_U64_DEPTH;
+  const uint64_t tile = depth ? kDTileElems : kTileElems;
   if (elems > static_cast<uint64_t>(kMaxTiles) * tile) return false;
+  if (!binned_fits(run, depth)) return false;
   if (run->splat_path == CFS_SPLAT_BINNED) return true;
   return static_cast<uint64_t>(run->n_points) * (run->n_iters - run->burn_in) >= (1ull << 20);
 }
@@ -403,6 +420,7 @@ bool scene_binned(const cfs_run *run, const cfs_image *img, int32_t n_objects) {
   if (run->n_iters == run->burn_in || run->n_points == 0) return false;
   const uint64_t elems = static_cast<uint64_t>(img->width) * img->height * img->channels;
   if (elems > static_cast<uint64_t>(kMaxTiles) * kTileElems) return false;
+  if (!binned_fits(run, false, static_cast<uint32_t>(n_objects))) return false;
   if (run->splat_path == CFS_SPLAT_BINNED) return true;
   return static_cast<uint64_t>(run->n_points) * (run->n_iters - run->burn_in) * n_objects >=
          (1ull << 20);
@@ -449,8 +467,11 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, cons
   } else if (img->kind == CFS_IMAGE_U64_DEPTH) {
     if (sys->final_kind != CFS_FINAL_TWIST_CAMERA)
       return fail(CFS_E_UNSUPPORTED, "a depth image needs the twist/camera transform");
-    if (!std::isfinite(img->near_plane))
-      return fail(CFS_E_INVALID, "near_plane is not finite");
+    // keys order splats by the FP32 bit pattern of their depth, which is
+    // the order of the depths only for non-negative values
+    if (!std::isfinite(img->near_plane) || !(img->near_plane >= 0.0f))
+      return fail(CFS_E_INVALID, "near_plane must be finite and >= 0 (got %g)",
+                  static_cast<double>(img->near_plane));
     job.depth = true;
   } else {
     return fail(CFS_E_INVALID, "cfs_chaos_game renders U32_COUNT or U64_DEPTH images");
@@ -460,6 +481,11 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, cons
   if (run->splat_path == CFS_SPLAT_BINNED && elems > static_cast<uint64_t>(kMaxTiles) * tile)
     return fail(CFS_E_UNSUPPORTED, "binned splat handles images of at most %u elements",
                 static_cast<unsigned>(kMaxTiles * tile));
+  if (run->splat_path == CFS_SPLAT_BINNED && run->n_iters > run->burn_in &&
+      !binned_fits(run, job.depth))
+    return fail(CFS_E_UNSUPPORTED,
+                "binned splat: %u splatted steps per point exceed one launch's record budget",
+                run->n_iters - run->burn_in);
   const size_t align = run->precision == CFS_PREC_F64 ? 8 : 4;
   if (final_points && reinterpret_cast<uintptr_t>(final_points) % align)
     return fail(CFS_E_INVALID, "final_points is not %zu-byte aligned", align);
@@ -534,6 +560,11 @@ extern "C" int cfs_chaos_scene(const cfs_system *sys, const cfs_object *objects,
   if (run->splat_path == CFS_SPLAT_BINNED && elems > static_cast<uint64_t>(kMaxTiles) * kTileElems)
     return fail(CFS_E_UNSUPPORTED, "binned splat handles images of at most %u elements",
                 static_cast<unsigned>(kMaxTiles * kTileElems));
+  if (run->splat_path == CFS_SPLAT_BINNED && run->n_iters > run->burn_in &&
+      !binned_fits(run, false, static_cast<uint32_t>(n_objects)))
+    return fail(CFS_E_UNSUPPORTED,
+                "binned splat: %u splatted steps x %d objects per point exceed one launch's "
+                "record budget", run->n_iters - run->burn_in, n_objects);
   SceneJob job;
   std::memset(&job, 0, sizeof job);
   job.precision = run->precision;

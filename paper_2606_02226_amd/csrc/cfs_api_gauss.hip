@@ -206,6 +206,13 @@ extern "C" int cfs_splat_backward(const cfs_system *sys, const cfs_run *run, con
   job.gb.tile_sums = reinterpret_cast<uint32_t *>(p + l.records + l.pos + 2 * l.table);
   job.S = reinterpret_cast<float2 *>(p + l.records + l.pos + 2 * l.table + l.sums);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (run->n_iters == run->burn_in || run->n_points == 0) {
+    // nothing is splatted: the density, hence the loss, does not depend on
+    // the maps and the gradient is exactly zero (+0.0f is the all-zero word)
+    return device_status(launch_clear_u32(reinterpret_cast<uint32_t *>(grad),
+                                          static_cast<size_t>(sys->n_maps) * 6, s),
+                         "cfs_splat_backward");
+  }
   const RunArgs ra = make_run_args(run);
   const bool splats = run->n_iters > run->burn_in;
   const uint32_t slice = gauss_slice(run);

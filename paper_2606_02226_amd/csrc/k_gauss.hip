@@ -597,7 +597,13 @@ static hipError_t launch_emit(const GaussJob &j, const GaussCkpt &ck, unsigned l
 }
 
 hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
-  if (j.ra.n_points == 0 || j.gb.n_chunks == 0) return hipSuccess;
+  if (j.ra.n_points == 0) return hipSuccess;
+  if (j.gb.n_chunks == 0) {
+    // no step is splatted (burn_in == n_iters): the emit kernel still walks
+    // the trajectory for its checkpoints; it stages nothing and never
+    // flushes, and the transpose of a table without rows is a no-op
+    return j.ck.ckpt ? launch_emit<false>(j, j.ck, j.dropped, s) : hipSuccess;
+  }
   hipError_t e = launch_emit<false>(j, j.ck, j.dropped, s);
   if (e != hipSuccess) return e;
   uint32_t p_max, per_part;

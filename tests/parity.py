@@ -50,3 +50,23 @@ def guard_band_violations(hist, sure, maybe):
     low = int(np.count_nonzero(h < sure))
     high = int(np.count_nonzero(h > sure + maybe))
     return low, high
+
+
+def depth_key_diff(got, ref):
+    """Compare two u64 depth|index key images (key = FP32 bits of a positive
+    depth << 32 | map index; all ones = empty).  Returns (occupied pixels,
+    pixels whose keys differ, pixels whose occupancy differs, largest
+    difference of the depth bits among differing occupied pixels).  Positive
+    FP32 values order as their bit patterns, so one unit of the depth bits is
+    one FP32 ulp of the depth."""
+    g = np.asarray(got, np.uint64).reshape(-1)
+    r = np.asarray(ref, np.uint64).reshape(-1)
+    empty = np.uint64(0xFFFFFFFFFFFFFFFF)
+    occ_g, occ_r = g != empty, r != empty
+    occ_diff = int(np.count_nonzero(occ_g != occ_r))
+    both = occ_g & occ_r
+    diff = both & (g != r)
+    gd = (g[diff] >> np.uint64(32)).astype(np.int64)
+    rd = (r[diff] >> np.uint64(32)).astype(np.int64)
+    ulps = int(np.max(np.abs(gd - rd))) if gd.size else 0
+    return int(np.count_nonzero(occ_r)), int(np.count_nonzero(diff)), occ_diff, ulps

@@ -381,3 +381,62 @@ def test_continued_run_rules(L):
                        0, None)
     assert rc == L.CFS_E_INVALID
     assert "exceeds n_iters" in lib.cfs_last_error().decode()
+
+
+def test_negative_near_plane_refused(L):
+    # depth keys order splats by the FP32 bits of their depth, which is the
+    # order of the depths only for non-negative values
+    lib = L.load()
+    s, keep = _system(L, dim=3, n=3, final_kind=2)
+    r = _run(L)
+    img = L.CfsImage(2, 16, 16, 1, (C.c_float * 2)(-1, -1), (C.c_float * 2)(1, 1), -0.5,
+                     C.c_void_p(256), C.c_void_p(512), None)  # never dereferenced
+    assert _call(L, s, r, img) == L.CFS_E_INVALID
+    assert "near_plane" in lib.cfs_last_error().decode()
+    img.near_plane = float("nan")
+    assert _call(L, s, r, img) == L.CFS_E_INVALID
+
+
+def test_binned_record_budget(L):
+    # one workgroup's records must fit one launch's budget (2^29 16-bit
+    # records): 43690 chunks of 12288, i.e. 1048560 splatted steps per point.
+    # One step more is refused for BINNED and takes the direct splat for AUTO.
+    lib = L.load()
+    s, keep = _system(L)
+    img = _image(L, W=64, H=64)
+    img.data = C.c_void_p(256)  # never dereferenced: nothing is launched
+    fits = L.CfsRun(0, 0, 1 << 12, 0, 1 << 20, 16, 0, 2)
+    assert lib.cfs_chaos_game_workspace(C.byref(s), C.byref(fits), C.byref(img)) > 0
+    over = L.CfsRun(0, 0, 1 << 12, 0, 1 << 20, 15, 0, 2)
+    assert lib.cfs_chaos_game_workspace(C.byref(s), C.byref(over), C.byref(img)) == 0
+    rc = lib.cfs_chaos_game(C.byref(s), C.byref(over), C.byref(img), None, None, None, None, 0,
+                            None)
+    assert rc == L.CFS_E_UNSUPPORTED
+    assert "record budget" in lib.cfs_last_error().decode()
+    auto = L.CfsRun(0, 0, 1 << 12, 0, 1 << 20, 15, 0, 0)
+    assert lib.cfs_chaos_game_workspace(C.byref(s), C.byref(auto), C.byref(img)) == 0
+    # a scene multiplies the records by its objects: 8 objects x 2^17 steps
+    objs = _objects(L, 8)
+    scene = L.CfsRun(0, 0, 1 << 12, 0, (1 << 17) + 8, 0, 0, 2)
+    assert lib.cfs_chaos_scene_workspace(C.byref(s), objs, 8, C.byref(scene),
+                                         C.byref(img)) == 0
+    rc = lib.cfs_chaos_scene(C.byref(s), objs, 8, C.byref(scene), C.byref(img), None, 0, None)
+    assert rc == L.CFS_E_UNSUPPORTED
+    assert "record budget" in lib.cfs_last_error().decode()
+
+
+def test_microbench_validation(L):
+    lib = L.load()
+    done = C.c_uint64(7)
+    assert lib.cfs_microbench(0, None, 64, 0, C.byref(done), None) == L.CFS_E_INVALID
+    assert lib.cfs_microbench(0, C.c_void_p(256), 64, 0, None, None) == L.CFS_E_INVALID
+    # placeholder addresses are never dereferenced: each call fails first
+    assert lib.cfs_microbench(0, C.c_void_p(255), 64, 0, C.byref(done), None) == L.CFS_E_INVALID
+    assert "aligned" in lib.cfs_last_error().decode()
+    assert lib.cfs_microbench(9, C.c_void_p(256), 64, 0, C.byref(done), None) == L.CFS_E_INVALID
+    assert "unknown microbenchmark" in lib.cfs_last_error().decode()
+    assert lib.cfs_microbench(0, C.c_void_p(256), 16, 0, C.byref(done), None) == L.CFS_E_INVALID
+    assert lib.cfs_microbench(1, C.c_void_p(256), 2, 1, C.byref(done), None) == L.CFS_E_INVALID
+    assert lib.cfs_microbench(3, C.c_void_p(256), 1024, 1, C.byref(done), None) == L.CFS_E_INVALID
+    assert lib.cfs_microbench(5, C.c_void_p(256), 1024, 1, C.byref(done), None) == L.CFS_E_INVALID
+    assert done.value == 7

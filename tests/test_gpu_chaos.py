@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from parity import guard_band_images, guard_band_violations, rel_l1
+from parity import depth_key_diff, guard_band_images, guard_band_violations, rel_l1
 
 pytestmark = pytest.mark.gpu
 
@@ -208,10 +208,14 @@ def test_menger_depth_parity(api, orc):
     got = got_img.to_numpy()
     ref = orc.chaos_depth(w["system"], w["run"], w["image"], w["image"]["near"])
     assert got["dropped"] == ref["dropped"]
-    assert rel_l1(got["density"], ref["density"]) <= 1e-4
-    same = np.mean(got["depth"] == ref["depth"])
-    print(f"menger f64: density relL1={rel_l1(got['density'], ref['density']):.2e} depth equal={same:.6f}")
-    assert same >= 1 - 1e-4
+    assert np.array_equal(got["density"], ref["density"])
+    occupied, differ, occ_diff, ulps = depth_key_diff(got["depth"], ref["depth"])
+    print(f"menger f64: keys differing {differ} of {occupied} (max {ulps} ulp)")
+    # FP64 depths differ from the oracle's by a few FP64 ulps (other rounding
+    # order and sine/cosine); their FP32 keys then differ only where the
+    # depth is within those ulps of an FP32 rounding boundary (~1e-8 per
+    # splat), by one FP32 ulp
+    assert occ_diff == 0 and ulps <= 1 and differ <= 2, (differ, ulps)
 
 
 def test_image_clear(api):
@@ -312,6 +316,27 @@ def test_binned_on_side_stream(api):
     torch.cuda.current_stream().wait_stream(side)
     got = img.data.cpu().numpy().view(np.uint32).astype(np.int64)
     assert np.array_equal(got, 2 * ref)
+
+
+def test_binned_side_stream_own_workspace(api):
+    # a call on a side stream that leaves the workspace to the binding, made
+    # outside that stream's context, followed at once by allocations and
+    # writes on the current stream: the binding's workspace must not be
+    # handed out again while the side stream still uses it
+    w = W.cfs_square(n_points=(1 << 22) + 517, side=1024)
+    ref = _image_of(api, w, "f64", "binned")["image"]
+    side = torch.cuda.Stream()
+    img = api.Image(w["image"], device=_dev())
+    side.wait_stream(torch.cuda.current_stream())
+    img.clear(side)
+    api.chaos_game(w["system"], w["run"], img, precision="f64", splat_path="binned", stream=side)
+    ws_bytes = api.chaos_workspace_bytes(w["system"], w["run"], img, "f64", "binned")
+    junk = [torch.full((ws_bytes // 4 + 1,), -1, dtype=torch.int32, device=_dev())
+            for _ in range(2)]
+    torch.cuda.current_stream().wait_stream(side)
+    got = img.data.cpu().numpy().view(np.uint32)
+    del junk
+    assert np.array_equal(got, ref)
 
 
 def test_binned_call_in_graph(api):
@@ -490,7 +515,8 @@ def test_depth_binned_vs_oracle(api, orc):
     ref = orc.chaos_depth(w["system"], w["run"], w["image"], w["image"]["near"])
     assert got["dropped"] == ref["dropped"]
     assert np.array_equal(got["density"], ref["density"])
-    assert np.mean(got["depth"] == ref["depth"]) >= 1 - 1e-4
+    occupied, differ, occ_diff, ulps = depth_key_diff(got["depth"], ref["depth"])
+    assert occ_diff == 0 and ulps <= 1 and differ <= 2, (differ, ulps)
 
 
 def test_full_size_menger(api, orc):
@@ -524,15 +550,51 @@ def test_full_size_menger(api, orc):
 # ---------------------------------------------------------------------------
 # The paper's circle primitive (non-affine maps, mixed kinds)
 # ---------------------------------------------------------------------------
+def _near_circle_singularity(orc, w, pid, eps):
+    """Whether the oracle's FP64 trajectory of point ``pid`` enters a circle
+    map within ``eps`` of the map's singular set: the origin (polar angle
+    undefined; an error d in p moves the angle by about d / |p|) or the
+    positive x-axis, where the polar angle taken in [0, 2 pi) jumps from 2 pi
+    to 0, so the image radius sqrt(angle / 2 pi) jumps from 1 to 0.  A
+    rounding difference there sends the two trajectories apart; elsewhere the
+    map is smooth and the error stays at rounding level."""
+    run, system = w["run"], w["system"]
+    circle_maps = {i for i, k in enumerate(system["kind"]) if k == "circle"}
+    T = run["n_iters"]
+    one = dict(run, n_points=1, point_offset=int(pid))
+    idx = orc.chaos_count(system, dict(one, burn_in=T), w["image"], want_indices=True)["indices"][0]
+    for t in range(1, T):          # p_t is the input of step t + 1
+        if int(idx[t]) not in circle_maps:
+            continue
+        p = orc.chaos_count(system, dict(one, n_iters=t, burn_in=t), w["image"],
+                            want_final=True)["final"][0]
+        if np.hypot(p[0], p[1]) < eps or (p[0] > -eps and abs(p[1]) < eps):
+            return True
+    return False
+
+
+def _check_circle_positions(orc, w, got, ref, bound, eps):
+    """Every final position within ``bound`` of the oracle's, except points
+    whose trajectory passes within ``eps`` of a circle map's singular set
+    (at most 1 in 1000)."""
+    err = np.abs(got["final"] - ref["final"]).max(axis=1)
+    out = np.flatnonzero(err > bound)
+    assert out.size <= max(1, err.size // 1000), out.size
+    for pid in out:
+        assert _near_circle_singularity(orc, w, pid, eps), (int(pid), float(err[pid]))
+    inside = np.delete(err, out)
+    return float(inside.max(initial=0.0)), int(out.size)
+
+
 def test_circle_fp64_parity(api, orc):
     w = W.circle(n_points=1 << 14)
     got = run_gpu(api, w, "f64", want_indices=True)
     ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True,
                           want_last=True, want_indices=True)
     assert np.array_equal(got["indices"], ref["indices"])
-    err = np.abs(got["final"] - ref["final"]).max(axis=1)
-    print(f"circle f64: max |dp| {err.max():.2e}, relL1 {rel_l1(got['image'], ref['image']):.2e}")
-    assert np.mean(err > 1e-9) <= 1e-3
+    worst, n_out = _check_circle_positions(orc, w, got, ref, 1e-9, 1e-6)
+    print(f"circle f64: max |dp| {worst:.2e} ({n_out} points past the singular set), "
+          f"relL1 {rel_l1(got['image'], ref['image']):.2e}")
     assert rel_l1(got["image"], ref["image"]) <= 1e-4
     assert got["dropped"] == ref["dropped"]
 
@@ -540,10 +602,16 @@ def test_circle_fp64_parity(api, orc):
 def test_circle_fp32_indices_and_measure(api, orc):
     w = W.circle(n_points=1 << 14)
     got = run_gpu(api, w, "f32", want_indices=True)
-    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_indices=True)
+    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True,
+                          want_indices=True)
     assert np.array_equal(got["indices"], ref["indices"])
+    # FP32 rounding (6e-8 relative per operation) grows to the 1e-5 bar only
+    # through the 1 / |p| of the polar angle near the origin or a change of
+    # side of the positive x-axis
+    worst, n_out = _check_circle_positions(orc, w, got, ref, 1e-5, 1e-2)
     l1 = rel_l1(got["image"], ref["image"])
-    print(f"circle f32: relL1 {l1:.2e}")
+    print(f"circle f32: max |dp| {worst:.2e} ({n_out} points past the singular set), "
+          f"relL1 {l1:.2e}")
     P = got["final"]
     u = P[:, 0] ** 2 + P[:, 1] ** 2
     assert np.all(u <= 1.0 + 1e-6) and abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / u.size)
@@ -583,9 +651,10 @@ def test_reuse_square_final_points(api, orc):
     ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True,
                           want_indices=True)
     assert np.array_equal(got["indices"], ref["indices"])
+    # the swirl and the affine maps are smooth: no point leaves rounding level
     err = np.abs(got["final"] - ref["final"]).max(axis=1)
     print(f"reuse square f64: max |dp| {err.max():.2e}")
-    assert np.mean(err > 1e-9) <= 1e-3
+    assert err.max() <= 1e-9, err.max()
     assert rel_l1(got["image"], ref["image"]) <= 1e-4
 
 

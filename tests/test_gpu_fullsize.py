@@ -1,0 +1,142 @@
+"""Full-size parity: the CFS square, batched, differentiable and 3D Menger
+workloads at the sizes the benchmark times, compared element by element with
+the FP64 oracle run over the whole workload (sharded by point range over the
+host cores; exact, since every point's random stream is keyed by its id and
+images are sums or minima over points).
+
+Bars (FP64 positions on the GPU, as the benchmark runs them):
+  count images   within 1e-4 relative L1 of the oracle's, dropped splats and
+                 per-channel totals equal (they depend only on the indices);
+  depth images   density equal; depth|index keys equal except where the FP32
+                 rounding of an FP64 depth can go either way, which moves a
+                 key by at most one FP32 ulp of the depth (counted, bounded);
+  densities      within 2e-5 of the maximum;
+  gradients      within 1e-4 relative L2 of the oracle's FP64 adjoint for the
+                 same upstream gradient.
+Each test prints the measured error.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import depth_key_diff, rel_l1
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_02226_amd import api as _api
+    return _api
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def test_full_cfs_square_image(api, orc):
+    """2^24 points x 32 iterations (8 burn-in), 4 x 2048 x 2048 u32, FP64,
+    binned: the whole image against the oracle's."""
+    w = W.cfs_square()
+    N, T, B = 1 << 24, 32, 8
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(w["system"], w["run"], img, precision="f64", splat_path="binned")
+    got = img.to_numpy()
+    t0 = time.perf_counter()
+    ref = orc.chaos_count_sharded(w["system"], w["run"], w["image"])
+    dt = time.perf_counter() - t0
+    h, r = got["image"].astype(np.int64), ref["image"].astype(np.int64)
+    l1 = rel_l1(h, r)
+    print(f"cfs_square full: rel L1 {l1:.3e}, differing pixels {np.count_nonzero(h != r)}, "
+          f"oracle {dt:.1f} s on {orc.host_threads()} threads")
+    assert got["dropped"] == ref["dropped"] == 0
+    assert int(h.sum()) == int(r.sum()) == N * (T - B)
+    assert np.array_equal(h.sum(axis=(1, 2)), r.sum(axis=(1, 2)))
+    assert l1 <= 1e-4, l1
+
+
+def test_full_menger_image(api, orc):
+    """2^26 points x 24 iterations (8 burn-in), 4096 x 4096 u64 keys + u32
+    density, FP64, binned: both images against the oracle's."""
+    w = W.menger()
+    N, T, B = 1 << 26, 24, 8
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(w["system"], w["run"], img, precision="f64")
+    got = img.to_numpy()
+    t0 = time.perf_counter()
+    ref = orc.chaos_depth_sharded(w["system"], w["run"], w["image"], w["image"]["near"])
+    dt = time.perf_counter() - t0
+    occupied, differ, occ_diff, ulps = depth_key_diff(got["depth"], ref["depth"])
+    dl1 = rel_l1(got["density"], ref["density"])
+    print(f"menger full: density rel L1 {dl1:.3e}, keys differing {differ} of {occupied} "
+          f"occupied (max {ulps} FP32 ulp of depth), oracle {dt:.1f} s")
+    assert got["dropped"] == ref["dropped"]
+    assert int(got["density"].astype(np.int64).sum()) + got["dropped"] == N * (T - B)
+    assert np.array_equal(got["density"], ref["density"])
+    assert occ_diff == 0
+    # an FP64 depth lands within a few FP64 ulps of an FP32 rounding boundary
+    # with probability ~1e-8 per splat: a handful of keys may differ, by one ulp
+    assert ulps <= 1 and differ <= max(4, occupied // 1_000_000), (differ, ulps)
+
+
+def test_full_differentiable(api, orc):
+    """2^20 points x 32 iterations (8 burn-in), sigma 1 px into 512 x 512,
+    checkpoints every 8: the density and the gradient of the L2 loss against
+    the target system's density, both against the oracle."""
+    w = W.differentiable()
+    N, T = w["run"]["n_points"], w["run"]["n_iters"]
+    every = w["ckpt_every"]
+    img = api.Image(w["image"], device=_dev()).clear()
+    ckpt = torch.empty((api.n_checkpoints(T, every), N, 2), dtype=torch.float32, device=_dev())
+    api.splat(w["system"], w["run"], img, 1.0, ckpt=ckpt, ckpt_every=every)
+    t0 = time.perf_counter()
+    D = orc.splat_gauss_sharded(w["system"], w["run"], w["image"], 1.0)
+    Dt = orc.splat_gauss_sharded(w["target_system"], w["run"], w["image"], 1.0)
+    G = (2.0 * (D - Dt)).astype(np.float32)
+    ref = orc.splat_gauss_backward_sharded(w["system"], w["run"], w["image"], 1.0,
+                                           G.astype(np.float64))
+    dt = time.perf_counter() - t0
+    got_D = img.data.cpu().numpy().astype(np.float64)
+    derr = float(np.max(np.abs(got_D - D)) / np.max(D))
+    g = api.splat_backward(w["system"], w["run"], img, 1.0, torch.from_numpy(G).to(_dev()),
+                           ckpt, every).cpu().numpy().astype(np.float64)
+    rel = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    print(f"differentiable full: density max err / max {derr:.2e}, gradient rel L2 {rel:.2e}, "
+          f"oracle {dt:.1f} s")
+    assert derr < 2e-5, derr
+    assert rel < 1e-4, rel
+
+
+def test_full_batched_every_instance(api, orc):
+    """256 systems (2..16 maps, 2^12..2^20 points, 256^2..1024^2 u32), one
+    graph launch, FP64: every instance's image against the oracle's."""
+    entries = W.batched()
+    images = [api.Image(w["image"], device=_dev()) for w in entries]
+    b = api.Batch(entries, images, precision="f64")
+    b.run()
+    torch.cuda.synchronize()
+    got = [img.to_numpy() for img in images]
+    b.close()
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    # largest instances first so the pool finishes together
+    order = sorted(range(len(entries)), key=lambda i: -entries[i]["run"]["n_points"])
+    with ThreadPoolExecutor(orc.host_threads()) as ex:
+        refs = dict(zip(order, ex.map(
+            lambda i: orc.chaos_count(entries[i]["system"], entries[i]["run"],
+                                      entries[i]["image"]), order)))
+    dt = time.perf_counter() - t0
+    worst, exact = 0.0, 0
+    for i, w in enumerate(entries):
+        l1 = rel_l1(got[i]["image"], refs[i]["image"])
+        worst = max(worst, l1)
+        exact += int(np.array_equal(got[i]["image"], refs[i]["image"]))
+        assert got[i]["dropped"] == refs[i]["dropped"], w["name"]
+        assert l1 <= 1e-4, (w["name"], l1)
+    print(f"batched full: {exact} of {len(entries)} instances equal to the oracle's, "
+          f"worst rel L1 {worst:.2e}, oracle {dt:.1f} s")

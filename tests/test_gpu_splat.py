@@ -55,16 +55,30 @@ def test_density_parity(api, orc, sigma):
     assert abs(got.sum() - ref.sum()) / ref.sum() < 1e-5
 
 
-def test_density_ragged_and_offimage(api, orc):
+# sigma 1 takes the 6-tap kernels, sigma in (1, 2.5] the 16-tap ones (15 or
+# 16 candidate taps per axis, margins of TAPS - 1 pixels beside tile 0)
+SIGMAS = [1.0, 1.01, 2.0, 2.5]
+
+
+@pytest.mark.parametrize("sigma", SIGMAS)
+def test_density_ragged_and_offimage(api, orc, sigma):
     # ragged image (not a multiple of the 32-pixel tile), window cutting the
-    # attractor so that footprints straddle and leave the image
+    # attractor so that footprints straddle and leave the image; the
+    # gradient through the same off-image footprints against the adjoint
     w = W.differentiable(n_points=3000, n_iters=21, burn_in=3)
     image = {"kind": "f32_density", "width": 77, "height": 45, "channels": 1,
              "lo": [0.1, 0.3], "hi": [0.8, 0.7]}
-    img, _ = gpu_forward(api, w["system"], w["run"], image, 1.0, every=5)
+    img, ckpt = gpu_forward(api, w["system"], w["run"], image, sigma, every=5)
     got = img.data.cpu().numpy().astype(np.float64)
-    ref = orc.splat_gauss(w["system"], w["run"], image, 1.0)
+    ref = orc.splat_gauss(w["system"], w["run"], image, sigma)
     assert np.max(np.abs(got - ref)) / np.max(ref) < 2e-5
+    G = np.random.default_rng(4).standard_normal((45, 77)).astype(np.float32)
+    g = api.splat_backward(w["system"], w["run"], img, sigma, torch.from_numpy(G).to(_dev()),
+                           ckpt, 5).cpu().numpy().astype(np.float64)
+    gref = orc.splat_gauss_backward(w["system"], w["run"], image, sigma, G.astype(np.float64))
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print(f"ragged sigma={sigma}: gradient rel L2 {rel:.2e}")
+    assert rel < 1e-4, rel
 
 
 def test_checkpoints_match_chaos_game(api):
@@ -89,16 +103,37 @@ def _upstream(orc, w, sigma=1.0):
     return 2.0 * (D - Dt)
 
 
-def test_gradient_vs_oracle_adjoint(api, orc):
+@pytest.mark.parametrize("sigma", SIGMAS)
+def test_gradient_vs_oracle_adjoint(api, orc, sigma):
     w = W.differentiable(n_points=1 << 16)
-    G = _upstream(orc, w).astype(np.float32)
-    img, ckpt = gpu_forward(api, w["system"], w["run"], w["image"])
-    g = api.splat_backward(w["system"], w["run"], img, 1.0, torch.from_numpy(G).to(_dev()),
+    G = _upstream(orc, w, sigma).astype(np.float32)
+    img, ckpt = gpu_forward(api, w["system"], w["run"], w["image"], sigma)
+    g = api.splat_backward(w["system"], w["run"], img, sigma, torch.from_numpy(G).to(_dev()),
                            ckpt, 8).cpu().numpy().astype(np.float64)
-    ref = orc.splat_gauss_backward(w["system"], w["run"], w["image"], 1.0, G.astype(np.float64))
+    ref = orc.splat_gauss_backward(w["system"], w["run"], w["image"], sigma,
+                                   G.astype(np.float64))
     rel = np.linalg.norm(g - ref) / np.linalg.norm(ref)
-    print(f"gradient vs oracle adjoint: rel L2 {rel:.2e}")
+    print(f"gradient vs oracle adjoint, sigma={sigma}: rel L2 {rel:.2e}")
     assert rel < 1e-4
+
+
+def test_no_splats_gradient_zero(api):
+    # burn_in == n_iters: nothing is splatted, the checkpoints are still
+    # written (equal to the plain chaos game's positions) and the gradient
+    # is exactly zero, also over a workspace and gradient full of NaNs
+    w = W.differentiable(n_points=3000, n_iters=16, burn_in=16, side=64)
+    img, ckpt = gpu_forward(api, w["system"], w["run"], w["image"], 1.0, 8)
+    assert torch.count_nonzero(img.data).item() == 0
+    fin = torch.empty((3000, 2), dtype=torch.float32, device=_dev())
+    cimg = api.Image({"kind": "u32_count", "width": 8, "height": 8, "channels": 1,
+                      "lo": [0, 0], "hi": [1, 1]}, device=_dev()).clear()
+    api.chaos_game(w["system"], dict(w["run"], n_iters=8, burn_in=8), cimg, final=fin)
+    assert torch.equal(ckpt[1], fin)
+    G = torch.randn((64, 64), dtype=torch.float32, device=_dev())
+    grad = torch.full((4, 6), float("nan"), dtype=torch.float32, device=_dev())
+    ws = torch.full((1 << 16,), 255, dtype=torch.uint8, device=_dev())
+    api.splat_backward(w["system"], w["run"], img, 1.0, G, ckpt, 8, grad=grad, workspace=ws)
+    assert torch.count_nonzero(grad).item() == 0
 
 
 def test_gradient_vs_finite_differences(api, orc):
