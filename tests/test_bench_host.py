@@ -24,8 +24,25 @@ def test_all_cores_oracle_figure_covers_every_splat():
     import oracle
     import workloads as W
     w = W.cfs_square(n_points=(1 << 13) + 7, side=256)
-    r = bench.cpu_baseline_all_cores(w, max_threads=3)
+    r, img = bench.cpu_baseline_all_cores(w, max_threads=3)
     assert r["kind"] == "oracle" and 1 <= r["cores"] <= 3 and r["value"] > 0
+    assert r["host"]["nproc"] >= 1 and r["host"]["affinity"] >= 1
     ref = oracle.chaos_count(w["system"], w["run"], w["image"])
     total = int(ref["image"].astype(np.int64).sum())
     assert r["splats"] == total == ((1 << 13) + 7) * 24 - ref["dropped"]
+    assert np.array_equal(img["image"], ref["image"])
+    err = bench.parity_error({"image": ref["image"], "dropped": ref["dropped"]}, img)
+    assert err["rel_l1"] == 0.0 and err["dropped_equal"]
+
+
+def test_all_cores_depth_figure_is_the_oracle_image():
+    import bench
+    import oracle
+    import workloads as W
+    w = W.menger(n_points=(1 << 12) + 3, side=256)
+    r, img = bench.cpu_baseline_all_cores(w, max_threads=3)
+    ref = oracle.chaos_depth(w["system"], w["run"], w["image"], w["image"]["near"])
+    assert np.array_equal(img["depth"], ref["depth"])
+    assert np.array_equal(img["density"], ref["density"])
+    err = bench.parity_error(dict(ref), img)
+    assert err["keys_differing"] == 0 and err["density_rel_l1"] == 0.0
