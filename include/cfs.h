@@ -105,9 +105,10 @@ enum { CFS_PREC_F32 = 0, CFS_PREC_F64 = 1 };
  * in LDS and writes them out as per-tile runs; a second kernel accumulates
  * every tile in LDS and merges it into the image (needs workspace; count
  * images of at most 2^25 elements, depth images of at most 2^24 pixels).
- * One workgroup's records must fit one launch's record budget (1 GiB), which
- * holds about 10^6 splatted steps per point (count images) or 1.4 x 10^5
- * (depth images); longer runs take DIRECT under AUTO and are refused
+ * One workgroup's records must fit one launch's record budget (2^29 16-bit
+ * count records or 2^28 8-byte depth records), which holds about 10^6
+ * splatted steps per point (count images) or 5.2 x 10^5 (depth images);
+ * longer runs take DIRECT under AUTO and are refused
  * (CFS_E_UNSUPPORTED) under BINNED.  AUTO picks BINNED for large runs that
  * qualify.  Both give bit-identical images (integer sums and minima do not
  * depend on order). */
@@ -369,14 +370,19 @@ typedef struct cfs_batch_item {
 
 /* Schedule of a batch.  blocks_per_item: 512-point blocks per work item
  * popped from the device queue (>= 1); emit_grid: persistent workgroups of
- * the chaos kernel (0 = two per compute unit); acc_grid: persistent
+ * the chaos kernels (0 = two per compute unit); acc_grid: persistent
  * workgroups of the tile-accumulate kernel (0 = two per compute unit);
- * splat_path: CFS_SPLAT_BINNED or CFS_SPLAT_DIRECT (CFS_SPLAT_AUTO = binned). */
+ * splat_path: CFS_SPLAT_BINNED or CFS_SPLAT_DIRECT (CFS_SPLAT_AUTO = binned);
+ * direct_below: the per-instance strategy of a BINNED plan -- an instance
+ * with fewer than direct_below splats (points x splatted steps) takes the
+ * direct splat (device atomics; no records, run tables or accumulate items),
+ * the others the binned splat (0 = every instance binned). */
 typedef struct cfs_plan {
   int32_t blocks_per_item;
   int32_t emit_grid;
   int32_t acc_grid;
   int32_t splat_path;
+  uint64_t direct_below;
 } cfs_plan;
 
 typedef struct cfs_batch cfs_batch; /* opaque, library-owned */
@@ -410,11 +416,19 @@ int cfs_batch_plan(const cfs_batch *batch, cfs_plan *out);
 void cfs_batch_destroy(cfs_batch *batch);
 
 /* Project-written autotuner: builds the batch with each candidate plan (both
- * splat paths, several work-item sizes and accumulate grids), times graph
- * replays with HIP events on `stream`, and writes the fastest plan to *out.
- * The images are overwritten by the trial runs. */
+ * splat paths, several work-item sizes and accumulate grids; then, for the
+ * fastest binned shape, several per-instance thresholds direct_below), times
+ * graph replays with HIP events on `stream`, and writes the fastest plan to
+ * *out.  The images are overwritten by the trial runs.
+ *   cache_path: host, nullable; a JSON Lines file of tuned plans keyed by
+ *     (device architecture name, compute units, signature of the batch's
+ *     shapes: per instance map count, equal or not, points, iterations,
+ *     burn-in, image size and channels, precision).  A matching line is
+ *     returned without timing anything (and without touching the images);
+ *     otherwise the tuned plan is appended as a new line.  An unreadable or
+ *     unwritable file is treated as empty / skipped. */
 int cfs_autotune(const cfs_batch_item *items, int32_t n_items, cfs_plan *out,
-                 void *stream);
+                 const char *cache_path, void *stream);
 
 /* Parity hook: out[i] = Philox4x32-10(ctrs[i], key(seed)) for i < n.
  * ctrs, out: device uint32 [n][4]. */

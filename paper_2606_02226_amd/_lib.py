@@ -75,7 +75,8 @@ class CfsBatchItem(C.Structure):
 
 class CfsPlan(C.Structure):
     _fields_ = [("blocks_per_item", C.c_int32), ("emit_grid", C.c_int32),
-                ("acc_grid", C.c_int32), ("splat_path", C.c_int32)]
+                ("acc_grid", C.c_int32), ("splat_path", C.c_int32),
+                ("direct_below", C.c_uint64)]
 
 
 _lib = None
@@ -124,7 +125,8 @@ def load():
     lib.cfs_batch_plan.argtypes = [P, C.POINTER(CfsPlan)]
     lib.cfs_batch_destroy.argtypes = [P]
     lib.cfs_batch_destroy.restype = None
-    lib.cfs_autotune.argtypes = [C.POINTER(CfsBatchItem), C.c_int32, C.POINTER(CfsPlan), P]
+    lib.cfs_autotune.argtypes = [C.POINTER(CfsBatchItem), C.c_int32, C.POINTER(CfsPlan),
+                                 C.c_char_p, P]
     lib.cfs_philox_dump.argtypes = [C.c_uint64, P, P, C.c_uint64, P]
     lib.cfs_timing_enable.argtypes = [C.c_int32]
     lib.cfs_timing_read.argtypes = [P, C.c_int32, P]

@@ -382,13 +382,15 @@ def _plan_struct(plan):
     p.emit_grid = int(plan.get("emit_grid", 0))
     p.acc_grid = int(plan.get("acc_grid", 0))
     p.splat_path = _lib.SPLAT_PATHS[plan.get("splat_path", "binned")]
+    p.direct_below = int(plan.get("direct_below", 0))
     return p
 
 
 def _plan_dict(p):
     names = {v: k for k, v in _lib.SPLAT_PATHS.items()}
     return {"blocks_per_item": p.blocks_per_item, "emit_grid": p.emit_grid,
-            "acc_grid": p.acc_grid, "splat_path": names[p.splat_path]}
+            "acc_grid": p.acc_grid, "splat_path": names[p.splat_path],
+            "direct_below": int(p.direct_below)}
 
 
 def _batch_items(entries, images, precision):
@@ -445,12 +447,14 @@ class Batch:
             pass
 
 
-def autotune(entries, images, precision="f32", stream=None):
+def autotune(entries, images, precision="f32", cache=None, stream=None):
     """Time the candidate plans on this batch (cfs_autotune); returns the
-    fastest plan as a dict.  Overwrites the images."""
+    fastest plan as a dict.  Overwrites the images.  ``cache``: path of a
+    JSON Lines plan cache (a matching entry is returned without timing)."""
     lib = _lib.load()
     items, keep = _batch_items(entries, images, precision)
     p = _lib.CfsPlan()
-    check(lib.cfs_autotune(items, len(entries), C.byref(p), _stream_handle(stream)),
-          "cfs_autotune")
+    check(lib.cfs_autotune(items, len(entries), C.byref(p),
+                           None if cache is None else str(cache).encode(),
+                           _stream_handle(stream)), "cfs_autotune")
     return _plan_dict(p)

@@ -262,10 +262,13 @@ extern "C" int cfs_image_clear(const cfs_image *img, void *stream) {
 
 namespace {
 
-// Records of one launch of the binned path: at most 1 GiB (2^29 16-bit or
-// 2^27 8-byte records), which keeps record indices within 31 bits and chunk
-// indices within 24 (the kernels index records in 32-bit arithmetic).
-uint64_t binned_record_budget(bool depth) { return depth ? (1ull << 27) : (1ull << 29); }
+// Records of one launch of the binned path: 2^29 16-bit count records
+// (1 GiB) or 2^28 8-byte depth records (2 GiB), which keeps record indices
+// within 31 bits and chunk indices within 24 (the kernels index records in
+// 32-bit arithmetic).  Each launch ends with a read-modify-write of the
+// image's occupied tiles, so depth runs (192 MiB of image) take the larger
+// budget: the 3D workload of 2^26 points x 16 splats needs four launches.
+uint64_t binned_record_budget(bool depth) { return depth ? (1ull << 28) : (1ull << 29); }
 
 uint64_t binned_block_records(const cfs_run *run, bool depth, uint32_t per_iter) {
   const uint64_t slots = depth ? kDSlots : kBinSlots;
@@ -276,7 +279,8 @@ uint64_t binned_block_records(const cfs_run *run, bool depth, uint32_t per_iter)
 }
 
 // Whether one workgroup's records fit the budget of a launch (runs of more
-// than about 10^6 splats per point do not, and take the direct splat).
+// than about 10^6 splats per point for counts, 5 x 10^5 for depth, do not,
+// and take the direct splat).
 bool binned_fits(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
   return binned_block_records(run, depth, per_iter) <= binned_record_budget(depth);
 }
@@ -309,12 +313,42 @@ bool use_binned(const cfs_run *run, const cfs_image *img) {
 
 size_t align_up(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-size_t binned_workspace(const cfs_run *run, const cfs_image *img, uint32_t per_iter = 1) {
+// Workspace of one launch of `points` points: records, the run table and its
+// transpose, and the transpose's column sums.
+size_t binned_workspace_for(uint32_t points, const cfs_run *run, const cfs_image *img,
+                            uint32_t per_iter = 1) {
   const uint32_t elems = static_cast<uint32_t>(img->width) * img->height * img->channels;
   const bool depth = img->kind == CFS_IMAGE_U64_DEPTH;
-  const BinPlan bp = bin_plan(binned_slice(run, depth, per_iter), run->n_iters, run->burn_in,
-                              elems, depth, per_iter);
+  const BinPlan bp = bin_plan(points, run->n_iters, run->burn_in, elems, depth, per_iter);
   return align_up(bp.records_bytes) + 2 * align_up(bp.table_bytes) + align_up(bp.sums_bytes);
+}
+
+size_t binned_workspace(const cfs_run *run, const cfs_image *img, uint32_t per_iter = 1) {
+  const bool depth = img->kind == CFS_IMAGE_U64_DEPTH;
+  return binned_workspace_for(binned_slice(run, depth, per_iter), run, img, per_iter);
+}
+
+// Points per launch of the binned path whose workspace takes at most `bytes`:
+// the most whole workgroups of points (at most binned_slice()) that fit, or 0
+// when one workgroup's records and tables alone do not.  The workspace grows
+// with the points of a launch, so a bisection over workgroups finds it.
+uint32_t binned_slice_within(const cfs_run *run, const cfs_image *img, size_t bytes) {
+  const bool depth = img->kind == CFS_IMAGE_U64_DEPTH;
+  const uint32_t top = binned_slice(run, depth);
+  const auto pts_of = [&](uint32_t blocks) {
+    return std::min<uint32_t>(top, blocks * static_cast<uint32_t>(kBinBlock));
+  };
+  uint32_t lo = 0, hi = (top + kBinBlock - 1) / kBinBlock;  // fits(lo) holds, answer <= hi
+  if (binned_workspace_for(pts_of(1), run, img) > bytes) return 0;
+  lo = 1;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (binned_workspace_for(pts_of(mid), run, img) <= bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return pts_of(lo);
 }
 
 // Point the binned arguments of one slice into the workspace.
@@ -436,10 +470,15 @@ extern "C" size_t cfs_chaos_game_workspace(const cfs_system *sys, const cfs_run 
   return binned_workspace(&cr, img);
 }
 
-extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, const cfs_image *img,
-                              void *final_points, uint8_t *last_index, uint8_t *indices,
-                              void *workspace, size_t workspace_bytes, void *stream) {
-  clear_error();
+namespace cfs {
+
+// Validation, packing and the launch plan of one cfs_chaos_game call.  With
+// `budget` > 0 the binned path cuts the run into launches whose workspace
+// takes at most `budget` bytes (a run that cannot be cut that fine takes the
+// direct splat under CFS_SPLAT_AUTO and is refused under CFS_SPLAT_BINNED).
+int chaos_prepare(const cfs_system *sys, const cfs_run *run_in, const cfs_image *img,
+                  void *final_points, uint8_t *last_index, uint8_t *indices, size_t budget,
+                  ChaosCall *call_out) {
   int rc = validate_system(sys);
   if (!rc) rc = validate_run(run_in);
   if (!rc) rc = validate_window(img);
@@ -448,12 +487,13 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, cons
     return fail(CFS_E_INVALID, "a continued run (iter_offset %u) reads its start from final_points",
                 run_in->iter_offset);
   // this call's view of the run: the part of the burn-in inside it
-  const cfs_run call = call_run(run_in);
-  const cfs_run *run = &call;
+  ChaosCall &cc = *call_out;
+  std::memset(&cc, 0, sizeof cc);
+  cc.run = call_run(run_in);
+  const cfs_run *run = &cc.run;
   if (run->splat_path < CFS_SPLAT_AUTO || run->splat_path > CFS_SPLAT_BINNED)
     return fail(CFS_E_INVALID, "unknown splat_path %d", run->splat_path);
-  ChaosJob job;
-  std::memset(&job, 0, sizeof job);
+  ChaosJob &job = cc.job;
   job.dim = sys->dim;
   job.final_kind = sys->final_kind;
   job.precision = run->precision;
@@ -490,14 +530,18 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, cons
   if (final_points && reinterpret_cast<uintptr_t>(final_points) % align)
     return fail(CFS_E_INVALID, "final_points is not %zu-byte aligned", align);
   job.binned = use_binned(run, img);
-  size_t need = 0;
   if (job.binned) {
-    need = binned_workspace(run, img);
-    if (!workspace || workspace_bytes < need)
-      return fail(CFS_E_WORKSPACE, "binned splat needs %zu bytes of workspace, got %zu", need,
-                  workspace ? workspace_bytes : static_cast<size_t>(0));
-    if (reinterpret_cast<uintptr_t>(workspace) % 256)
-      return fail(CFS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    cc.slice = budget ? binned_slice_within(run, img, budget) : binned_slice(run, job.depth);
+    if (cc.slice == 0) {
+      if (run->splat_path == CFS_SPLAT_BINNED)
+        return fail(CFS_E_UNSUPPORTED,
+                    "binned splat: one workgroup's records (%u splatted steps per point) "
+                    "exceed the %zu-byte workspace limit",
+                    run->n_iters - run->burn_in, budget);
+      job.binned = false;  // AUTO: the direct splat needs no workspace
+    } else {
+      cc.need = binned_workspace_for(cc.slice, run, img);
+    }
   }
   if (sys->dim == 2)
     rc = pack_table<2>(sys, &job.mt2, &job.equal);
@@ -514,32 +558,59 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, cons
   job.out.last_index = last_index;
   job.out.indices = indices;
   job.out.dropped = img->dropped;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool timed = timing_begin_call();
-  if (!job.binned) {
-    job.ev = timed ? timing_slice() : nullptr;
-    return device_status(launch_chaos(job, s), "cfs_chaos_game");
-  }
+  cc.elems = static_cast<uint32_t>(elems);
+  return CFS_OK;
+}
 
-  // binned: slices of at most binned_slice() points share the workspace
-  const uint32_t slice = binned_slice(run, job.depth);
+// Enqueue a prepared call: the direct kernel, or the binned launches of at
+// most cc.slice points each, one after the other on the stream, all sharing
+// `workspace` (cc.need bytes, checked by the caller).  `timed`: record the
+// measurement hook's phase events.
+int chaos_launch(const ChaosCall &cc, void *workspace, bool timed, hipStream_t s) {
+  const ChaosJob &job = cc.job;
+  const cfs_run *run = &cc.run;
+  if (!job.binned) {
+    ChaosJob dj = job;
+    dj.ev = timed ? timing_slice() : nullptr;
+    return device_status(launch_chaos(dj, s), "cfs_chaos_game");
+  }
   const size_t real_bytes = run->precision == CFS_PREC_F64 ? sizeof(double) : sizeof(float);
-  for (uint32_t done = 0; done < run->n_points; done += slice) {
-    const uint32_t pts = std::min(slice, run->n_points - done);
-    const BinPlan bp = bin_plan(pts, run->n_iters, run->burn_in, static_cast<uint32_t>(elems), job.depth);
+  for (uint32_t done = 0; done < run->n_points; done += cc.slice) {
+    const uint32_t pts = std::min(cc.slice, run->n_points - done);
+    const BinPlan bp = bin_plan(pts, run->n_iters, run->burn_in, cc.elems, job.depth);
     ChaosJob sj = job;
     sj.ra.n_points = pts;
     sj.ra.point_offset = run->point_offset + done;
-    if (final_points)
-      sj.out.final_points = static_cast<char *>(final_points) + static_cast<size_t>(done) * sys->dim * real_bytes;
-    if (last_index) sj.out.last_index = last_index + done;
-    if (indices) sj.out.indices = indices + static_cast<size_t>(done) * run->n_iters;
+    if (job.out.final_points)
+      sj.out.final_points = static_cast<char *>(job.out.final_points) +
+                            static_cast<size_t>(done) * job.dim * real_bytes;
+    if (job.out.last_index) sj.out.last_index = job.out.last_index + done;
+    if (job.out.indices) sj.out.indices = job.out.indices + static_cast<size_t>(done) * run->n_iters;
     bind_workspace(&sj.ba, bp, workspace);
     sj.ev = timed ? timing_slice() : nullptr;
-    rc = device_status(launch_chaos_binned(sj, s), "cfs_chaos_game");
+    const int rc = device_status(launch_chaos_binned(sj, s), "cfs_chaos_game");
     if (rc) return rc;
   }
   return CFS_OK;
+}
+
+}  // namespace cfs
+
+extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, const cfs_image *img,
+                              void *final_points, uint8_t *last_index, uint8_t *indices,
+                              void *workspace, size_t workspace_bytes, void *stream) {
+  clear_error();
+  ChaosCall cc;
+  int rc = chaos_prepare(sys, run_in, img, final_points, last_index, indices, 0, &cc);
+  if (rc) return rc;
+  if (cc.job.binned) {
+    if (!workspace || workspace_bytes < cc.need)
+      return fail(CFS_E_WORKSPACE, "binned splat needs %zu bytes of workspace, got %zu", cc.need,
+                  workspace ? workspace_bytes : static_cast<size_t>(0));
+    if (reinterpret_cast<uintptr_t>(workspace) % 256)
+      return fail(CFS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  }
+  return chaos_launch(cc, workspace, timing_begin_call(), static_cast<hipStream_t>(stream));
 }
 
 extern "C" size_t cfs_chaos_scene_workspace(const cfs_system *sys, const cfs_object *objects,

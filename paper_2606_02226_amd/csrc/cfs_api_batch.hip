@@ -2,7 +2,9 @@
 // descriptors, work queues, records), HIP-graph capture and replay, per-frame
 // updates, and the autotuner that picks a schedule by timing graph replays.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "cfs.h"
@@ -25,7 +27,7 @@ struct cfs_batch {
   uint32_t *d_queues = nullptr;
   uint16_t *d_records = nullptr;
   uint16_t *d_tables = nullptr;
-  uint32_t n_items32 = 0, n_items64 = 0, n_acc = 0, n_trans = 0;
+  uint32_t n_items32 = 0, n_items64 = 0, n_direct32 = 0, n_direct64 = 0, n_acc = 0, n_trans = 0;
   std::vector<int32_t> n_maps;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -78,7 +80,7 @@ int validate_item(const cfs_batch_item &it, int i) {
 int normalise_plan(const cfs_plan *in, int cus, cfs_plan *out) {
   // default: four blocks per item (256 random systems: 7.59 ms per graph
   // launch against 7.76 with one; the accumulate grid barely matters)
-  cfs_plan p{4, 0, 0, CFS_SPLAT_BINNED};
+  cfs_plan p{4, 0, 0, CFS_SPLAT_BINNED, 0};
   if (in) p = *in;
   if (p.blocks_per_item < 1 || p.blocks_per_item > 1024)
     return fail(CFS_E_INVALID, "plan.blocks_per_item must be in 1..1024");
@@ -125,7 +127,7 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
   if (rc) return rc;
 
   std::vector<InstDesc> desc(n_items);
-  std::vector<EmitItem> emit;
+  std::vector<EmitItem> emit, direct;
   std::vector<AccItem> acc;
   std::vector<TransItem> trans;
   uint64_t rec_total = 0, table_total = 0;
@@ -144,6 +146,17 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
     d.dropped = it.img.dropped;
     d.elems = static_cast<uint32_t>(it.img.width) * it.img.height * it.img.channels;
     const BinPlan bp = bin_plan(it.run.n_points, it.run.n_iters, it.run.burn_in, d.elems);
+    // the plan's per-instance strategy: the direct splat for the whole batch,
+    // or for the instances with fewer splats than direct_below
+    const uint64_t n_splats =
+        static_cast<uint64_t>(it.run.n_points) * (it.run.n_iters - it.run.burn_in);
+    if (p.splat_path == CFS_SPLAT_DIRECT || n_splats < p.direct_below) {
+      d.n_tiles = bp.n_tiles;
+      for (uint32_t blk = 0; blk < bp.blocks; blk += p.blocks_per_item)
+        direct.push_back(EmitItem{static_cast<uint32_t>(i), blk,
+                                  std::min<uint32_t>(p.blocks_per_item, bp.blocks - blk)});
+      continue;
+    }
     const bool splats = it.run.n_iters > it.run.burn_in;
     d.n_tiles = bp.n_tiles;
     d.flushes = splats ? bp.flushes : 0;
@@ -180,6 +193,13 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
   });
   uint32_t n32 = 0;
   for (const EmitItem &it : emit) n32 += desc[it.inst].precision == 0 ? 1u : 0u;
+  std::stable_sort(direct.begin(), direct.end(), [&](const EmitItem &a, const EmitItem &b2) {
+    const InstDesc &da = desc[a.inst], &db = desc[b2.inst];
+    if (da.precision != db.precision) return da.precision < db.precision;
+    return da.ra.n_points > db.ra.n_points;
+  });
+  uint32_t d32 = 0;
+  for (const EmitItem &it : direct) d32 += desc[it.inst].precision == 0 ? 1u : 0u;
   // accumulate items by expected record count, largest first
   std::stable_sort(acc.begin(), acc.end(), [&](const AccItem &a, const AccItem &b2) {
     const double wa = static_cast<double>(a.c_hi - a.c_lo) / desc[a.inst].n_tiles;
@@ -194,14 +214,17 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
   b->cus = cus;
   b->n_items32 = n32;
   b->n_items64 = static_cast<uint32_t>(emit.size()) - n32;
+  b->n_direct32 = d32;
+  b->n_direct64 = static_cast<uint32_t>(direct.size()) - d32;
   b->n_acc = static_cast<uint32_t>(acc.size());
   b->n_trans = static_cast<uint32_t>(trans.size());
   for (int i = 0; i < n_items; ++i) b->n_maps.push_back(items[i].sys.n_maps);
   HIP_TRY(hipMalloc(&b->d_desc, sizeof(InstDesc) * n_items), "hipMalloc(descriptors)");
-  HIP_TRY(hipMalloc(&b->d_items, sizeof(EmitItem) * std::max<size_t>(emit.size(), 1)), "hipMalloc(items)");
+  HIP_TRY(hipMalloc(&b->d_items, sizeof(EmitItem) * std::max<size_t>(emit.size() + direct.size(), 1)),
+          "hipMalloc(items)");
   HIP_TRY(hipMalloc(&b->d_acc, sizeof(AccItem) * std::max<size_t>(acc.size(), 1)), "hipMalloc(acc)");
   HIP_TRY(hipMalloc(&b->d_queues, kQueues * sizeof(uint32_t)), "hipMalloc(queues)");
-  if (p.splat_path == CFS_SPLAT_BINNED) {
+  if (!emit.empty()) {
     HIP_TRY(hipMalloc(&b->d_records, std::max<uint64_t>(rec_total, 1) * sizeof(uint16_t)),
             "hipMalloc(records)");
     HIP_TRY(hipMalloc(&b->d_tables, std::max<uint64_t>(table_total, 1) * sizeof(uint16_t)),
@@ -220,6 +243,10 @@ extern "C" int cfs_batch_create(const cfs_batch_item *items, int32_t n_items, co
   if (!emit.empty())
     HIP_TRY(hipMemcpy(b->d_items, emit.data(), sizeof(EmitItem) * emit.size(), hipMemcpyHostToDevice),
             "copy items");
+  if (!direct.empty())
+    HIP_TRY(hipMemcpy(b->d_items + emit.size(), direct.data(), sizeof(EmitItem) * direct.size(),
+                      hipMemcpyHostToDevice),
+            "copy direct items");
   if (!acc.empty())
     HIP_TRY(hipMemcpy(b->d_acc, acc.data(), sizeof(AccItem) * acc.size(), hipMemcpyHostToDevice),
             "copy accumulate items");
@@ -243,6 +270,9 @@ extern "C" int cfs_batch_run(cfs_batch *b, void *stream) {
     L.items = b->d_items;
     L.n_items32 = b->n_items32;
     L.n_items64 = b->n_items64;
+    L.ditems = b->d_items + b->n_items32 + b->n_items64;
+    L.n_direct32 = b->n_direct32;
+    L.n_direct64 = b->n_direct64;
     L.acc = b->d_acc;
     L.n_acc = b->n_acc;
     L.queues = b->d_queues;
@@ -253,7 +283,6 @@ extern "C" int cfs_batch_run(cfs_batch *b, void *stream) {
     L.n_trans = b->n_trans;
     L.emit_grid = static_cast<uint32_t>(b->plan.emit_grid);
     L.acc_grid = static_cast<uint32_t>(b->plan.acc_grid);
-    L.direct = b->plan.splat_path == CFS_SPLAT_DIRECT;
     e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return device_status(e, "hipStreamBeginCapture");
     const hipError_t le = launch_batch(L, b->capture_stream);
@@ -312,52 +341,159 @@ extern "C" void cfs_batch_destroy(cfs_batch *b) {
   free_batch(b);
 }
 
+namespace {
+
+// Signature of a batch's shapes (FNV-1a, 64 bits): what the timing of a plan
+// depends on, not the map coefficients.
+std::string batch_signature(const cfs_batch_item *items, int32_t n_items) {
+  uint64_t h = 1469598103934665603ull;
+  const auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xFFu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix(static_cast<uint64_t>(n_items));
+  for (int i = 0; i < n_items; ++i) {
+    const cfs_batch_item &it = items[i];
+    mix(static_cast<uint64_t>(it.sys.n_maps));
+    mix(it.sys.prob ? 1u : 0u);
+    mix(it.run.n_points);
+    mix(it.run.n_iters);
+    mix(it.run.burn_in);
+    mix(static_cast<uint64_t>(it.img.width) << 32 | static_cast<uint32_t>(it.img.height));
+    mix(static_cast<uint64_t>(it.img.channels));
+    mix(static_cast<uint64_t>(it.run.precision));
+  }
+  char buf[17];
+  std::snprintf(buf, sizeof buf, "%016llx", static_cast<unsigned long long>(h));
+  return buf;
+}
+
+// The last line of the cache file with this key, if any.
+bool cache_lookup(const char *path, const std::string &arch, int cus, const std::string &sig,
+                  cfs_plan *out) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    char a[256], sg[32];
+    int c = 0, bpi = 0, eg = 0, ag = 0, sp = 0;
+    unsigned long long db = 0;
+    const int got = std::sscanf(
+        line,
+        "{\"arch\": \"%255[^\"]\", \"cus\": %d, \"signature\": \"%31[0-9a-f]\", \"plan\": "
+        "{\"blocks_per_item\": %d, \"emit_grid\": %d, \"acc_grid\": %d, \"splat_path\": %d, "
+        "\"direct_below\": %llu}",
+        a, &c, sg, &bpi, &eg, &ag, &sp, &db);
+    if (got == 8 && arch == a && c == cus && sig == sg) {
+      *out = cfs_plan{bpi, eg, ag, sp, static_cast<uint64_t>(db)};
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char *path, const std::string &arch, int cus, const std::string &sig,
+                 const cfs_plan &p, float ms) {
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"arch\": \"%s\", \"cus\": %d, \"signature\": \"%s\", \"plan\": "
+               "{\"blocks_per_item\": %d, \"emit_grid\": %d, \"acc_grid\": %d, "
+               "\"splat_path\": %d, \"direct_below\": %llu}, \"ms\": %.4f}\n",
+               arch.c_str(), cus, sig.c_str(), p.blocks_per_item, p.emit_grid, p.acc_grid,
+               p.splat_path, static_cast<unsigned long long>(p.direct_below), ms);
+  std::fclose(f);
+}
+
+// Milliseconds per graph launch of a batch built with plan c: a capture and
+// three warm-up launches, then three timed launches.
+int time_plan(const cfs_batch_item *items, int32_t n_items, const cfs_plan &c, void *stream,
+              hipEvent_t ev0, hipEvent_t ev1, float *ms) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  cfs_batch *b = nullptr;
+  int rc = cfs_batch_create(items, n_items, &c, &b);
+  if (rc) return rc;
+  for (int r = 0; r < 4 && !rc; ++r) rc = cfs_batch_run(b, stream);
+  if (!rc) {
+    hipError_t e = hipEventRecord(ev0, s);
+    for (int r = 0; r < 3 && !rc; ++r) rc = cfs_batch_run(b, stream);
+    if (e == hipSuccess) e = hipEventRecord(ev1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, ev0, ev1);
+    if (e != hipSuccess && !rc) rc = device_status(e, "autotune timing");
+  }
+  cfs_batch_destroy(b);
+  return rc;
+}
+
+}  // namespace
+
 extern "C" int cfs_autotune(const cfs_batch_item *items, int32_t n_items, cfs_plan *out,
-                            void *stream) {
+                            const char *cache_path, void *stream) {
   clear_error();
   if (!out) return fail(CFS_E_INVALID, "out is NULL");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int dev = 0, cus = 0;
+  if (!items || n_items < 1) return fail(CFS_E_INVALID, "need at least one batch item");
+  for (int i = 0; i < n_items; ++i) {
+    const int rc = validate_item(items[i], i);
+    if (rc) return rc;
+  }
+  int dev = 0;
   hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
   if (e != hipSuccess) return device_status(e, "device query");
-  std::vector<cfs_plan> cands;
-  for (int bpi : {1, 2, 4})
-    for (int accm : {2, 4}) cands.push_back(cfs_plan{bpi, 2 * cus, accm * cus, CFS_SPLAT_BINNED});
-  for (int bpi : {1, 4}) cands.push_back(cfs_plan{bpi, 2 * cus, 0, CFS_SPLAT_DIRECT});
+  const int cus = prop.multiProcessorCount;
+  const std::string arch = prop.gcnArchName;
+  const std::string sig = batch_signature(items, n_items);
+  if (cache_path && cache_lookup(cache_path, arch, cus, sig, out)) return CFS_OK;
+
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if ((e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess) {
     if (ev0) hipEventDestroy(ev0);
     return device_status(e, "hipEventCreate");
   }
+  // shapes: work-item sizes and accumulate grids of the binned splat, and
+  // the direct splat for the whole batch
+  std::vector<cfs_plan> cands;
+  for (int bpi : {1, 2, 4})
+    for (int accm : {2, 4}) cands.push_back(cfs_plan{bpi, 2 * cus, accm * cus, CFS_SPLAT_BINNED, 0});
+  for (int bpi : {1, 4}) cands.push_back(cfs_plan{bpi, 2 * cus, 0, CFS_SPLAT_DIRECT, 0});
   float best = 1e30f;
   cfs_plan best_plan{};
   int rc = CFS_OK;
   for (const cfs_plan &c : cands) {
-    cfs_batch *b = nullptr;
-    rc = cfs_batch_create(items, n_items, &c, &b);
+    float ms = 0.0f;
+    rc = time_plan(items, n_items, c, stream, ev0, ev1, &ms);
     if (rc) break;
-    rc = cfs_batch_run(b, stream);  // warm-up (captures the graph)
-    for (int r = 0; r < 3 && !rc; ++r) rc = cfs_batch_run(b, stream);
-    if (!rc) {
-      hipEventRecord(ev0, s);
-      for (int r = 0; r < 3 && !rc; ++r) rc = cfs_batch_run(b, stream);
-      hipEventRecord(ev1, s);
-      e = hipEventSynchronize(ev1);
+    if (ms < best) {
+      best = ms;
+      best_plan = c;
+    }
+  }
+  // then the per-instance strategy on the fastest binned shape: instances
+  // below a splat threshold take the direct splat
+  if (!rc && best_plan.splat_path == CFS_SPLAT_BINNED) {
+    const cfs_plan shape = best_plan;
+    for (uint64_t below : {1ull << 17, 1ull << 19, 1ull << 21}) {
+      cfs_plan c = shape;
+      c.direct_below = below;
       float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-      if (e != hipSuccess && !rc) rc = device_status(e, "autotune timing");
-      if (!rc && ms < best) {
+      rc = time_plan(items, n_items, c, stream, ev0, ev1, &ms);
+      if (rc) break;
+      if (ms < best) {
         best = ms;
         best_plan = c;
       }
     }
-    cfs_batch_destroy(b);
-    if (rc) break;
   }
   hipEventDestroy(ev0);
   hipEventDestroy(ev1);
   if (rc) return rc;
   *out = best_plan;
+  if (cache_path) cache_store(cache_path, arch, cus, sig, best_plan, best / 3.0f);
   return CFS_OK;
 }

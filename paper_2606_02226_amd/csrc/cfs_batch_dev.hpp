@@ -8,7 +8,9 @@
 namespace cfs {
 
 constexpr int kClearParts = 16;
-constexpr int kQueues = 3;  // FP32 items, FP64 items, accumulate items
+// binned FP32 items, binned FP64 items, accumulate items, direct FP32 items,
+// direct FP64 items
+constexpr int kQueues = 5;
 
 // One instance as the persistent kernels see it (device memory).
 struct InstDesc {
@@ -40,8 +42,10 @@ struct TransItem {
 struct BatchLaunch {
   InstDesc *desc;
   uint32_t n_inst;
-  const EmitItem *items;  // FP32 instances' items, then FP64 instances' items
+  const EmitItem *items;  // binned instances: FP32 items, then FP64 items
   uint32_t n_items32, n_items64;
+  const EmitItem *ditems;  // direct-splat instances: FP32 items, then FP64 items
+  uint32_t n_direct32, n_direct64;
   const AccItem *acc;
   uint32_t n_acc;
   uint32_t *queues;  // [kQueues]
@@ -51,7 +55,6 @@ struct BatchLaunch {
   uint16_t *ctables;  // [chunk][tile + 1] per instance: run starts within the chunk
   uint16_t *tables;   // [tile + 1][chunk] per instance
   uint32_t emit_grid, acc_grid;
-  bool direct;
 };
 
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t stream);

@@ -292,15 +292,57 @@ __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_m
 }
 
 // Depth tile t: LDS minimum of the keys (depth bits << 32 | index) and LDS
-// counts of every chunk's records, then merged into the image (min) and the
-// density (sum).  Every thread calls it; keys/counts are kDTileElems each.
+// counts of every chunk's records of the tile, then merged into the image
+// (min) and the density (sum) by the one workgroup that owns the tile.  Runs
+// are walked by groups of 2^log2g lanes, each lane loading two records per
+// 16-byte load from the even record at or below the run start (records
+// outside [start, end) are skipped; a chunk holds an even number of records,
+// so no load leaves it), kDRunsInFlight runs per group at a time.  The
+// kernel waits on memory, so the run bounds of the next round are loaded
+// while the current round's records are counted, and every lane keeps
+// kDRunsInFlight record loads in flight.  Every thread calls it; keys and
+// counts are kDTileElems each.
+constexpr int kDRunsInFlight = 8;
+static_assert(kDCap % 2 == 0, "depth chunks hold whole 16-byte record pairs");
+
+__device__ __forceinline__ void depth_record(unsigned long long *keys, uint32_t *counts,
+                                             uint32_t x, uint32_t y) {
+  const uint32_t off = x & (kDTileElems - 1);
+  atomicMin(&keys[off], (static_cast<unsigned long long>(y) << 32) | (x >> kDTileBits));
+  atomicAdd(&counts[off], 1u);
+}
+
+__device__ __forceinline__ void depth_pair(unsigned long long *keys, uint32_t *counts, uint4 v,
+                                           uint32_t at, uint32_t s, uint32_t e) {
+  if (at >= s && at < e) depth_record(keys, counts, v.x, v.y);
+  if (at + 1u >= s && at + 1u < e) depth_record(keys, counts, v.z, v.w);
+}
+
+// Bounds [s, e) (record indices of the launch) of kDRunsInFlight runs of
+// the tile: those of chunks c0, c0 + stride, ...; empty past the last chunk.
+// Record indices of a launch stay below 2^31 (the launch budget).
+__device__ __forceinline__ void depth_run_bounds(const uint16_t *__restrict__ row0,
+                                                 const uint16_t *__restrict__ row1, uint32_t c0,
+                                                 uint32_t stride, uint32_t n_chunks,
+                                                 uint32_t s[kDRunsInFlight],
+                                                 uint32_t e[kDRunsInFlight]) {
+#pragma unroll
+  for (int u = 0; u < kDRunsInFlight; ++u) {
+    const uint32_t c = c0 + u * stride;
+    const uint32_t base = c * kDCap;
+    s[u] = c < n_chunks ? base + row0[c] : 0u;
+    e[u] = c < n_chunks ? base + row1[c] : 0u;
+  }
+}
+
 __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
                                              const uint16_t *__restrict__ tile_start,
                                              uint32_t n_chunks, uint32_t elems,
                                              unsigned long long *__restrict__ img,
                                              uint32_t *__restrict__ density, uint32_t t,
-                                             unsigned long long *keys, uint32_t *counts) {
-  const int tid = threadIdx.x;
+                                             uint32_t log2g, unsigned long long *keys,
+                                             uint32_t *counts) {
+  const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < kDTileElems; i += kDAccBlock) {
     keys[i] = ~0ull;
     counts[i] = 0u;
@@ -308,21 +350,32 @@ __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
   __syncthreads();
   const uint16_t *row0 = tile_start + static_cast<size_t>(t) * n_chunks;
   const uint16_t *row1 = row0 + n_chunks;
-  for (uint32_t c = tid; c < n_chunks; c += kDAccBlock) {
-    const uint32_t s = c * kDCap + row0[c], e = c * kDCap + row1[c];
-    for (uint32_t i = s; i < e; i += 4u) {
-      uint2 v[4];
+  const uint32_t g = 1u << log2g, lane = tid & (g - 1u);
+  const uint32_t groups = kDAccBlock >> log2g;
+  const uint32_t round = groups * kDRunsInFlight;
+  uint32_t s[kDRunsInFlight], e[kDRunsInFlight];
+  depth_run_bounds(row0, row1, tid >> log2g, groups, n_chunks, s, e);
+  for (uint32_t c0 = tid >> log2g; c0 < n_chunks; c0 += round) {
+    uint4 v[kDRunsInFlight];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = i + u < e ? rec[i + u] : make_uint2(kInvalid, 0u);
+    for (int u = 0; u < kDRunsInFlight; ++u) {
+      const uint32_t i = (s[u] & ~1u) + 2u * lane;
+      v[u] = i < e[u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    // the next round's bounds, loaded while this round's records arrive
+    uint32_t s2[kDRunsInFlight], e2[kDRunsInFlight];
+    depth_run_bounds(row0, row1, c0 + round, groups, n_chunks, s2, e2);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (v[u].x == kInvalid) continue;
-        const uint32_t off = v[u].x & (kDTileElems - 1);
-        const unsigned long long key =
-            (static_cast<unsigned long long>(v[u].y) << 32) | (v[u].x >> kDTileBits);
-        atomicMin(&keys[off], key);
-        atomicAdd(&counts[off], 1u);
-      }
+    for (int u = 0; u < kDRunsInFlight; ++u) {
+      const uint32_t i = (s[u] & ~1u) + 2u * lane;
+      depth_pair(keys, counts, v[u], i, s[u], e[u]);
+      for (uint32_t j = i + 2u * g; j < e[u]; j += 2u * g)
+        depth_pair(keys, counts, *reinterpret_cast<const uint4 *>(rec + j), j, s[u], e[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kDRunsInFlight; ++u) {
+      s[u] = s2[u];
+      e[u] = e2[u];
     }
   }
   __syncthreads();

@@ -270,6 +270,19 @@ __device__ __forceinline__ double sqrt_f64(double a) {
   return a > 1e-300 ? g : 0.0;
 }
 
+// FP64 reciprocal for the camera's perspective divide: the hardware estimate
+// and two Newton steps (within an ulp or two of 1 / a; one estimate and four
+// FMAs in place of the two correctly rounded divisions' longer sequences).
+// 0 gives infinity, whose projection is then dropped with the depth test.
+__device__ __forceinline__ double rcp_f64(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(r, fma(-a, r, 1.0), r);
+  r = fma(r, fma(-a, r, 1.0), r);
+  return r;
+}
+
+__device__ __forceinline__ float rcp_r(float a) { return 1.0f / a; }
+__device__ __forceinline__ double rcp_r(double a) { return rcp_f64(a); }
 __device__ __forceinline__ void sincos_r(float a, float *s, float *c) { sincosf(a, s, c); }
 __device__ __forceinline__ void sincos_r(double a, double *s, double *c) { sincos_f64(a, s, c); }
 __device__ __forceinline__ float sqrt_r(float a) { return sqrtf(a); }
@@ -314,8 +327,9 @@ __device__ __forceinline__ void final_transform(const float *__restrict__ fp, co
     const real vx = fp[4] * tx + fp[5] * wy + fp[6] * tz + fp[7];
     const real vy = fp[8] * tx + fp[9] * wy + fp[10] * tz + fp[11];
     const real vz = fp[12] * tx + fp[13] * wy + fp[14] * tz + fp[15];
-    q[0] = static_cast<real>(fp[16]) * vx / vz;
-    q[1] = static_cast<real>(fp[17]) * vy / vz;
+    const real inv = rcp_r(vz);
+    q[0] = static_cast<real>(fp[16]) * vx * inv;
+    q[1] = static_cast<real>(fp[17]) * vy * inv;
     *depth = vz;
   } else {
     q[0] = p[0];

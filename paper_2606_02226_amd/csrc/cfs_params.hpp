@@ -72,12 +72,24 @@ constexpr int kAccBlock = 1024;  // two per CU: 8 waves per SIMD
 
 // Binned depth splat: records are (pixel | index << 24, FP32 depth bits),
 // kDSlots per lane per chunk, sorted by tiles of kDTileElems pixels whose
-// u64 keys and u32 counts fit in LDS together.
-constexpr int kDSlots = 12;
+// u64 keys and u32 counts fit in LDS together.  Sixteen slots: the 64 KB
+// stage, the tile counts and a 20-map FP64 table keep two chaos workgroups
+// per CU, and a run of 16 splatted steps per point fills one whole chunk.
+constexpr int kDSlots = 16;
 constexpr uint32_t kDCap = static_cast<uint32_t>(kBinBlock) * kDSlots;
 constexpr int kDTileBits = 13;
 constexpr uint32_t kDTileElems = 1u << kDTileBits;
-constexpr int kDAccBlock = 512;
+constexpr int kDAccBlock = 1024;  // one per CU (96 KB of LDS): 4 waves per SIMD
+
+// Lanes per run of the depth accumulate, 2^log2g: the smallest group whose
+// one pass of two records per lane covers a run of the mean length plus one
+// (the even record below the start).
+__host__ __device__ inline uint32_t depth_run_lanes_log2(uint64_t mean_run) {
+  const uint64_t need = mean_run + 1u;
+  uint32_t lg = 0;
+  while (lg < 5 && (2ull << lg) < need) ++lg;
+  return lg;
+}
 
 // The count accumulate aims at this many workgroups (two per CU of MI355X).
 constexpr uint32_t kAccTargetGroups = 512;

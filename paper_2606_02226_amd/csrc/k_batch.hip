@@ -2,8 +2,9 @@
 // persistent workgroups that pop work items from a device queue.
 //
 // An instance is one 2D affine system with its run and image.  Emit items are
-// (instance, first 1024-point block, block count); accumulate items are
-// (instance, image tile).  Each item loads its instance's descriptor (map
+// (instance, first 512-point block, block count); accumulate items are
+// (instance, image tile, chunk range).  Each instance takes the binned or
+// the direct splat, as the plan's per-instance threshold says.  Each item loads its instance's descriptor (map
 // table and thresholds into LDS) and runs exactly the device functions of a
 // plain run, so every instance's image is bit-identical to cfs_chaos_game's.
 // The queues hold a known number of items and every workgroup leaves when a
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(kBinBlock) void k_batch_direct(const InstDesc *__re
 }
 
 // Clear every image (kClearParts workgroups per instance), zero the dropped
-// counters and reset both queues.  Plain stores only (graph-safe).
+// counters and reset every queue.  Plain stores only (graph-safe).
 __global__ void k_batch_clear(const InstDesc *__restrict__ desc, uint32_t n_inst, uint32_t *queues) {
   const uint32_t inst = blockIdx.x / kClearParts;
   const uint32_t part = blockIdx.x % kClearParts;
@@ -154,16 +155,8 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
                      b.queues);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // FP32 instances first, then FP64 ones, each from its own queue
-  if (b.direct) {
-    if (b.n_items32)
-      hipLaunchKernelGGL(k_batch_direct<float>, dim3(b.emit_grid), dim3(kBinBlock), 0, s, b.desc,
-                         b.items, b.n_items32, b.queues + 0);
-    if (b.n_items64)
-      hipLaunchKernelGGL(k_batch_direct<double>, dim3(b.emit_grid), dim3(kBinBlock), 0, s, b.desc,
-                         b.items + b.n_items32, b.n_items64, b.queues + 1);
-    return hipGetLastError();
-  }
+  // binned instances (FP32 then FP64, each from its own queue), then the
+  // direct-splat instances, then the binned instances' transposes and tiles
   if (b.n_items32)
     hipLaunchKernelGGL(k_batch_emit<float>, dim3(b.emit_grid), dim3(kBinBlock), 0, s, b.desc, b.items,
                        b.n_items32, b.queues + 0, b.records, b.ctables, b.tables);
@@ -171,6 +164,12 @@ hipError_t launch_batch(const BatchLaunch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_emit<double>, dim3(b.emit_grid), dim3(kBinBlock), 0, s, b.desc,
                        b.items + b.n_items32, b.n_items64, b.queues + 1, b.records, b.ctables,
                        b.tables);
+  if (b.n_direct32)
+    hipLaunchKernelGGL(k_batch_direct<float>, dim3(b.emit_grid), dim3(kBinBlock), 0, s, b.desc,
+                       b.ditems, b.n_direct32, b.queues + 3);
+  if (b.n_direct64)
+    hipLaunchKernelGGL(k_batch_direct<double>, dim3(b.emit_grid), dim3(kBinBlock), 0, s, b.desc,
+                       b.ditems + b.n_direct32, b.n_direct64, b.queues + 4);
   if (b.n_trans)
     hipLaunchKernelGGL(k_batch_transpose, dim3(b.n_trans), dim3(256), 0, s, b.desc, b.trans,
                        b.ctables, b.tables);

@@ -35,12 +35,15 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_binned(MapTable<DIM> mt, Wi
                                                        out, blockIdx.x, stage, cnt, wsum);
 }
 
+// The map table sits in dynamic LDS sized for the system's own maps, so that
+// the 64 KB stage leaves room for two workgroups per CU.
 template <typename real, bool EQUAL>
 __global__ __launch_bounds__(kBinBlock) void k_chaos_depth_binned(MapTable<3> mt, Window win,
                                                                   RunArgs ra, FinalArgs fa,
                                                                   float near_plane, BinArgs ba,
                                                                   Outputs out) {
-  __shared__ real table[kMaxMaps * RowStride<real, 3>::value];
+  extern __shared__ __align__(16) unsigned char dyn_lds[];
+  real *table = reinterpret_cast<real *>(dyn_lds);
   __shared__ uint32_t th[kThWords];
   __shared__ uint2 stage[kDCap];
   __shared__ uint32_t cnt[kMaxTiles];
@@ -51,17 +54,6 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_depth_binned(MapTable<3> mt
   chaos_depth_block<real, EQUAL ? kSelEqual : kSelTable>(table, th, mt.n_maps, mt.n_search,
                                                          win, ra, fa.p, near_plane,
                                                          ba, out, blockIdx.x, stage, cnt, wsum);
-}
-
-__global__ __launch_bounds__(kDAccBlock) void k_depth_accumulate(const uint2 *__restrict__ rec,
-                                                                 const uint16_t *__restrict__ tile_start,
-                                                                 uint32_t n_chunks, uint32_t elems,
-                                                                 unsigned long long *img,
-                                                                 uint32_t *density) {
-  __shared__ unsigned long long keys[kDTileElems];
-  __shared__ uint32_t counts[kDTileElems];
-  depth_tile_accumulate(rec, tile_start, n_chunks, elems, img, density,
-                        xcd_item(blockIdx.x, gridDim.x), keys, counts);
 }
 
 // Record total of tile t over all chunks, from the transpose's column sums
@@ -79,6 +71,28 @@ __device__ inline uint32_t tile_total(const uint32_t *__restrict__ sums, uint32_
 #pragma unroll
   for (int w = 0; w < kAccBlock / 64; ++w) total += red[w];
   return total;
+}
+
+// One workgroup per depth tile, taken in XCD-contiguous order (the runs of
+// neighbouring tiles share cache lines in every chunk); a tile without
+// records (from the transpose's column sums) ends at once, and the lanes per
+// run follow the tile's own mean run length.
+__global__ __launch_bounds__(kDAccBlock) void k_depth_accumulate(const uint2 *__restrict__ rec,
+                                                                 const uint16_t *__restrict__ tile_start,
+                                                                 const uint32_t *__restrict__ sums,
+                                                                 uint32_t n_rb, uint32_t n_chunks,
+                                                                 uint32_t elems,
+                                                                 unsigned long long *img,
+                                                                 uint32_t *density) {
+  __shared__ unsigned long long keys[kDTileElems];
+  __shared__ uint32_t counts[kDTileElems];
+  __shared__ uint32_t red[kDAccBlock / 64];
+  static_assert(kDAccBlock == kAccBlock, "tile_total sums over kAccBlock lanes");
+  const uint32_t t = xcd_item(blockIdx.x, gridDim.x);
+  const uint32_t total = tile_total(sums, n_rb, t, red);
+  if (total == 0) return;  // the same value in every lane
+  depth_tile_accumulate(rec, tile_start, n_chunks, elems, img, density, t,
+                        depth_run_lanes_log2(total / n_chunks), keys, counts);
 }
 
 // One workgroup per (image tile, chunk range); the parts of a tile are
@@ -164,7 +178,7 @@ BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t e
                            : static_cast<size_t>(bp.n_chunks) * kChunkCap * sizeof(uint16_t);
   bp.table_bytes = static_cast<size_t>(bp.n_tiles + 1) * bp.n_chunks * sizeof(uint16_t);  // each of two
   bp.n_rb = (bp.n_chunks + 63) / 64;
-  bp.sums_bytes = depth ? 0 : static_cast<size_t>(bp.n_tiles + 1) * bp.n_rb * sizeof(uint32_t);
+  bp.sums_bytes = static_cast<size_t>(bp.n_tiles + 1) * bp.n_rb * sizeof(uint32_t);
   return bp;
 }
 
@@ -228,22 +242,24 @@ static hipError_t launch_binned_real(const ChaosJob &j, hipStream_t s) {
 template <typename real>
 static hipError_t launch_depth_binned(const ChaosJob &j, hipStream_t s) {
   const uint32_t blocks = (j.ra.n_points + kBinBlock - 1) / kBinBlock;
+  const size_t table_bytes = static_cast<size_t>(j.mt3.n_maps) * RowStride<real, 3>::value * sizeof(real);
   mark_phase(j.ev, 0, s);
   if (j.equal)
-    hipLaunchKernelGGL((k_chaos_depth_binned<real, true>), dim3(blocks), dim3(kBinBlock), 0, s, j.mt3,
-                       j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
+    hipLaunchKernelGGL((k_chaos_depth_binned<real, true>), dim3(blocks), dim3(kBinBlock),
+                       table_bytes, s, j.mt3, j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
   else
-    hipLaunchKernelGGL((k_chaos_depth_binned<real, false>), dim3(blocks), dim3(kBinBlock), 0, s,
-                       j.mt3, j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
+    hipLaunchKernelGGL((k_chaos_depth_binned<real, false>), dim3(blocks), dim3(kBinBlock),
+                       table_bytes, s, j.mt3, j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
   hipError_t e = hipGetLastError();
   mark_phase(j.ev, 1, s);
   if (e == hipSuccess && j.ba.n_chunks != 0)
-    e = launch_transpose(j.ba.chunk_start, j.ba.tile_start, j.ba.n_chunks, j.ba.n_tiles + 1, s);
+    e = launch_transpose(j.ba.chunk_start, j.ba.tile_start, j.ba.n_chunks, j.ba.n_tiles + 1, s,
+                         j.ba.tile_sums);
   mark_phase(j.ev, 2, s);
   if (e == hipSuccess && j.ba.n_chunks != 0) {
     hipLaunchKernelGGL(k_depth_accumulate, dim3(j.ba.n_tiles), dim3(kDAccBlock), 0, s,
-                       j.ba.drecords, j.ba.tile_start, j.ba.n_chunks, j.ba.elems,
-                       static_cast<unsigned long long *>(j.img), j.density);
+                       j.ba.drecords, j.ba.tile_start, j.ba.tile_sums, j.ba.n_rb, j.ba.n_chunks,
+                       j.ba.elems, static_cast<unsigned long long *>(j.img), j.density);
     e = hipGetLastError();
   }
   mark_phase(j.ev, 3, s);

@@ -35,12 +35,21 @@ def small_batch(n=32, max_points=1 << 14):
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
-@pytest.mark.parametrize("path", ["binned", "direct"])
+@pytest.mark.parametrize("path", ["binned", "direct", "mixed"])
 def test_batch_equals_plain(api, precision, path):
+    """Every instance equals its plain run, whether the batch's instances
+    all take the binned splat, all the direct one, or each the one the plan's
+    threshold gives it (mixed: instances below 2^18 splats direct)."""
     entries = small_batch()
     images = [api.Image(w["image"], device=_dev()) for w in entries]
-    b = api.Batch(entries, images, plan={"splat_path": path, "blocks_per_item": 2},
-                  precision=precision)
+    plan = {"splat_path": "binned" if path == "mixed" else path, "blocks_per_item": 2}
+    if path == "mixed":
+        plan["direct_below"] = 1 << 18
+        splats = [w["run"]["n_points"] * (w["run"]["n_iters"] - w["run"]["burn_in"])
+                  for w in entries]
+        assert min(splats) < 1 << 18 <= max(splats)   # both strategies are exercised
+    b = api.Batch(entries, images, plan=plan, precision=precision)
+    assert b.plan()["direct_below"] == plan.get("direct_below", 0)
     b.run()
     for w, img in zip(entries, images):
         got = img.to_numpy()
@@ -118,11 +127,38 @@ def test_batch_edge_instances(api):
     b.close()
 
 
-def test_autotune_plan_is_valid(api):
+def test_autotune_plan_is_valid(api, tmp_path):
+    """The tuned plan renders every instance exactly; it is written to the
+    cache file under the device's architecture, CU count and the batch's
+    signature, and a second call returns it from the cache without running
+    anything (the images it would overwrite keep their contents)."""
+    import json
     entries = small_batch(n=16)
     images = [api.Image(w["image"], device=_dev()) for w in entries]
-    plan = api.autotune(entries, images)
+    cache = tmp_path / "plans.jsonl"
+    plan = api.autotune(entries, images, cache=cache)
     assert plan["splat_path"] in ("binned", "direct") and plan["blocks_per_item"] >= 1
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    entry = json.loads(lines[0])
+    props = torch.cuda.get_device_properties(_dev())
+    assert entry["cus"] == props.multi_processor_count
+    assert entry["arch"].startswith("gfx950")
+    assert entry["plan"]["blocks_per_item"] == plan["blocks_per_item"]
+    assert entry["plan"]["direct_below"] == plan["direct_below"]
+    assert entry["ms"] > 0
+    for img in images:
+        img.data.fill_(7)
+    again = api.autotune(entries, images, cache=cache)
+    torch.cuda.synchronize()
+    assert again == plan
+    assert all(int(img.data.min()) == 7 == int(img.data.max()) for img in images)
+    assert len(cache.read_text().splitlines()) == 1
+    # another batch shape misses the cache and appends its own line
+    other = small_batch(n=5)
+    oimgs = [api.Image(w["image"], device=_dev()) for w in other]
+    api.autotune(other, oimgs, cache=cache)
+    assert len(cache.read_text().splitlines()) == 2
     b = api.Batch(entries, images, plan=plan)
     b.run()
     for w, img in zip(entries, images):
