@@ -224,6 +224,29 @@ int cfs_chaos_game(const cfs_system *sys, const cfs_run *run,
                    uint8_t *last_index, uint8_t *indices, void *workspace,
                    size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, hosts that forbid allocation): the same
+ * chaos game as cfs_chaos_game, same arguments and results, with the
+ * binned splat's records and run tables in a fixed array of
+ * CFS_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * (until the process ends) instead of a caller workspace.  A binned run is
+ * cut into point-range launches whose records and tables fit that array
+ * (the result is the same: the random streams are keyed by point id).
+ * A run whose single workgroup of points does not fit (from about 6 x 10^4
+ * splatted steps per point for depth images to 2.6 x 10^5 for small count
+ * images) takes the direct splat under CFS_SPLAT_AUTO and fails
+ * with CFS_E_UNSUPPORTED under CFS_SPLAT_BINNED.  Calls no hipMalloc or
+ * hipFree; the first call on a device looks up that device's array (the
+ * stream must belong to the current device).  Every call on one GPU shares
+ * its array, which keeps the last call's contents (nothing in it needs
+ * clearing): calls that overlap on one GPU -- concurrent streams or host
+ * threads -- race and must be serialised by the caller.  The measurement
+ * hook does not time these calls. */
+#define CFS_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int cfs_chaos_game_noalloc(const cfs_system *sys, const cfs_run *run,
+                           const cfs_image *img, void *final_points,
+                           uint8_t *last_index, uint8_t *indices, void *stream);
+
 /* Measurement hook.  While enabled, every cfs_chaos_game call (up to 256
  * calls between reads) records HIP events on its stream before its chaos
  * kernel, after it, after the run-table transpose and after the tile

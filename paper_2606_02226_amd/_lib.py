@@ -33,7 +33,7 @@ EXPORTS = (
     "cfs_splat_backward", "cfs_batch_create", "cfs_batch_run", "cfs_batch_update",
     "cfs_batch_plan", "cfs_batch_destroy", "cfs_autotune", "cfs_philox_dump",
     "cfs_chaos_scene_workspace", "cfs_chaos_scene", "cfs_l2_loss_workspace", "cfs_l2_loss",
-    "cfs_timing_enable", "cfs_timing_read", "cfs_microbench",
+    "cfs_timing_enable", "cfs_timing_read", "cfs_microbench", "cfs_chaos_game_noalloc",
 )
 MICROBENCH = {"copy": 0, "dev_add_u32": 1, "dev_min_u64": 2, "lds_add_u32": 3,
               "lds_min_u64": 4, "philox": 5, "lds_add_u64": 6}
@@ -107,6 +107,8 @@ def load():
     lib.cfs_chaos_game_workspace.restype = C.c_size_t
     lib.cfs_chaos_game.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun),
                                    C.POINTER(CfsImage), P, P, P, P, C.c_size_t, P]
+    lib.cfs_chaos_game_noalloc.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun),
+                                           C.POINTER(CfsImage), P, P, P, P]
     lib.cfs_splat_workspace.argtypes = [C.POINTER(CfsSystem), C.POINTER(CfsRun),
                                         C.POINTER(CfsImage), C.c_float]
     lib.cfs_splat_workspace.restype = C.c_size_t

@@ -169,6 +169,21 @@ def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
     return image
 
 
+def chaos_game_noalloc(system, run, image, *, precision="f32", final=None, last=None,
+                       indices=None, splat_path="auto", stream=None):
+    """Enqueue cfs_chaos_game_noalloc: the chaos game of :func:`chaos_game`
+    with the binned splat's records in the library's fixed per-GPU array
+    (no workspace, nothing allocated here or in the library).  Calls that
+    overlap on one GPU race on that array."""
+    lib = _lib.load()
+    sysc = system if isinstance(system, System) else System(system)
+    runc = run_struct(run, precision, splat_path)
+    check(lib.cfs_chaos_game_noalloc(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
+                                     _ptr(final), _ptr(last), _ptr(indices),
+                                     _stream_handle(stream)), "cfs_chaos_game_noalloc")
+    return image
+
+
 def microbench(kind, buf, ops=0, stream=None):
     """Enqueue one ceiling probe (cfs_microbench) over the uint8 device
     tensor ``buf``; returns the operations (bytes for 'copy') it issues.
