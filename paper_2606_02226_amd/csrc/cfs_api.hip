@@ -207,6 +207,21 @@ int pack_table(const cfs_system *s, MapTable<DIM> *mt, bool *equal) {
         mt->flags |= kFlagCircle;
       }
   if (s->compose == CFS_COMPOSE_REUSE) mt->flags |= kFlagReuse;
+  // one linear part for every map (compared bit for bit): the kernels then
+  // gather only the translations; a multiple of the identity (and no
+  // negative-zero translation) takes one FMA per coordinate
+  mt->lin = mt->flags & kFlagCircle ? kLinGeneral : kLinShared;
+  for (int m = 1; m < n && mt->lin != kLinGeneral; ++m)
+    if (std::memcmp(&mt->coef[m * C], &mt->coef[0], sizeof(float) * DIM * DIM) != 0)
+      mt->lin = kLinGeneral;
+  if (mt->lin == kLinShared) {
+    bool scalar = true;
+    for (int r = 0; r < DIM; ++r)
+      for (int c = 0; c < DIM; ++c)
+        scalar = scalar && (r == c ? mt->coef[r * DIM + c] == mt->coef[0] : mt->coef[r * DIM + c] == 0.0f);
+    for (int i = 0; i < n * DIM; ++i) scalar = scalar && !(s->b[i] == 0.0f && std::signbit(s->b[i]));
+    if (scalar) mt->lin = kLinScalar;
+  }
   uint64_t th[CFS_MAX_MAPS];
   const int rc = make_thresholds(s->prob, n, th);
   if (rc) return rc;
@@ -291,7 +306,7 @@ bool binned_fits(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
 uint32_t binned_slice(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
   uint64_t max_blocks = binned_record_budget(depth) / binned_block_records(run, depth, per_iter);
   if (max_blocks < 1) max_blocks = 1;
-  uint64_t pts = max_blocks * kBinBlock;
+  uint64_t pts = max_blocks * (depth ? kDBlock : kBinBlock);
   if (pts > (1ull << 24)) pts = 1ull << 24;
   if (pts > run->n_points) pts = run->n_points;
   return static_cast<uint32_t>(pts);
@@ -335,10 +350,9 @@ size_t binned_workspace(const cfs_run *run, const cfs_image *img, uint32_t per_i
 uint32_t binned_slice_within(const cfs_run *run, const cfs_image *img, size_t bytes) {
   const bool depth = img->kind == CFS_IMAGE_U64_DEPTH;
   const uint32_t top = binned_slice(run, depth);
-  const auto pts_of = [&](uint32_t blocks) {
-    return std::min<uint32_t>(top, blocks * static_cast<uint32_t>(kBinBlock));
-  };
-  uint32_t lo = 0, hi = (top + kBinBlock - 1) / kBinBlock;  // fits(lo) holds, answer <= hi
+  const uint32_t block = depth ? kDBlock : kBinBlock;
+  const auto pts_of = [&](uint32_t blocks) { return std::min<uint32_t>(top, blocks * block); };
+  uint32_t lo = 0, hi = (top + block - 1) / block;  // fits(lo) holds, answer <= hi
   if (binned_workspace_for(pts_of(1), run, img) > bytes) return 0;
   lo = 1;
   while (lo < hi) {

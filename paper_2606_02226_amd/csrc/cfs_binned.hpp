@@ -9,19 +9,22 @@ namespace cfs {
 
 constexpr uint32_t kInvalid = 0xFFFFFFFFu;
 constexpr int kWaves = kBinBlock / 64;
+constexpr int kDWaves = kDBlock / 64;
 
 // Exclusive prefix sum of a[0..n) in place (n <= kMaxTiles), returns the
-// total.  Thread i owns kScanPer consecutive entries.  Every thread of the
-// workgroup must call it.
-constexpr int kScanPer = (kMaxTiles + kBinBlock - 1) / kBinBlock;
-
+// total.  Thread i of the BLOCK threads owns kMaxTiles / BLOCK consecutive
+// entries.  Every thread of the workgroup must call it; wsum holds
+// BLOCK / 64 + 1 words.
+template <int BLOCK = kBinBlock>
 __device__ inline uint32_t block_exclusive_scan(uint32_t *a, uint32_t n, uint32_t *wsum) {
+  constexpr int kPer = (kMaxTiles + BLOCK - 1) / BLOCK;
+  constexpr int kW = BLOCK / 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const uint32_t i0 = static_cast<uint32_t>(tid) * kScanPer;
-  uint32_t v[kScanPer];
+  const uint32_t i0 = static_cast<uint32_t>(tid) * kPer;
+  uint32_t v[kPer];
   uint32_t s = 0;
 #pragma unroll
-  for (int q = 0; q < kScanPer; ++q) {
+  for (int q = 0; q < kPer; ++q) {
     v[q] = i0 + q < n ? a[i0 + q] : 0u;
     s += v[q];
   }
@@ -34,24 +37,24 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t *a, uint32_t n, uint32_
   if (lane == 63) wsum[w] = incl;
   __syncthreads();
   if (w == 0) {
-    const uint32_t x = lane < kWaves ? wsum[lane] : 0u;
+    const uint32_t x = lane < kW ? wsum[lane] : 0u;
     uint32_t xi = x;
 #pragma unroll
-    for (int d = 1; d < kWaves; d <<= 1) {
+    for (int d = 1; d < kW; d <<= 1) {
       const uint32_t y = __shfl_up(xi, d, 64);
       if (lane >= d) xi += y;
     }
-    if (lane < kWaves) wsum[lane] = xi - x;
-    if (lane == kWaves - 1) wsum[kWaves] = xi;
+    if (lane < kW) wsum[lane] = xi - x;
+    if (lane == kW - 1) wsum[kW] = xi;
   }
   __syncthreads();
   uint32_t run = wsum[w] + incl - s;
 #pragma unroll
-  for (int q = 0; q < kScanPer; ++q) {
+  for (int q = 0; q < kPer; ++q) {
     if (i0 + q < n) a[i0 + q] = run;
     run += v[q];
   }
-  const uint32_t total = wsum[kWaves];
+  const uint32_t total = wsum[kW];
   __syncthreads();
   return total;
 }
@@ -97,11 +100,15 @@ __device__ inline void flush_chunk(uint32_t *stage, uint32_t *cnt, uint32_t *wsu
 // compiles the circle-map and reuse branches (`flags`) and continued runs
 // (RunArgs::iter_block); without it they are compiled out, which keeps the
 // affine copy-transform loop at its register count.
-template <typename real, int DIM, int FINAL, int SEL, bool GENERAL = true>
+// LIN != kLinGeneral (with !GENERAL): the maps share one linear part `A` and
+// `table` is the translations-only table.
+template <typename real, int DIM, int FINAL, int SEL, bool GENERAL = true, int LIN = kLinGeneral>
 __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_maps, int n_search,
                                    int flags, const Window &win, const RunArgs &ra,
                                    const float *fparams, const BinArgs &ba, const Outputs &out,
-                                   uint32_t block, uint32_t *stage, uint32_t *cnt, uint32_t *wsum) {
+                                   uint32_t block, uint32_t *stage, uint32_t *cnt, uint32_t *wsum,
+                                   const SharedLinear<real, DIM> &A = {}) {
+  static_assert(!(GENERAL && LIN != kLinGeneral), "the shared-linear-part loop is the fast variant's");
   if constexpr (!GENERAL) flags = 0;
   const int tid = threadIdx.x;
   const uint32_t n = block * kBinBlock + tid;
@@ -133,7 +140,10 @@ __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_
       k = select_index<SEL>(u, th, n_maps, n_search);
       if (active && out.indices)
         out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
-      apply_map<real, DIM>(table, k, p, flags);
+      if constexpr (LIN != kLinGeneral)
+        apply_shared_map<real, DIM, LIN>(table, A, k, p);
+      else
+        apply_map<real, DIM>(table, k, p, flags);
       if constexpr (DIM == 2 && FINAL != kFinalIdentity) {
         if (flags & kFlagReuse) {
           real g[2], dz;
@@ -196,15 +206,15 @@ __device__ inline void flush_depth_chunk(uint2 *stage, uint32_t *cnt, uint32_t *
                                          uint32_t chunk, const BinArgs &ba) {
   __syncthreads();
   const int tid = threadIdx.x;
-  const uint32_t total = block_exclusive_scan(cnt, ba.n_tiles, wsum);
+  const uint32_t total = block_exclusive_scan<kDBlock>(cnt, ba.n_tiles, wsum);
   const uint32_t base = chunk * kDCap;
   uint16_t *row = ba.chunk_start + static_cast<size_t>(chunk) * (ba.n_tiles + 1);
-  for (uint32_t t = tid; t <= ba.n_tiles; t += kBinBlock)
+  for (uint32_t t = tid; t <= ba.n_tiles; t += kDBlock)
     row[t] = static_cast<uint16_t>(t < ba.n_tiles ? cnt[t] : total);
   uint2 e[kDSlots];
 #pragma unroll
   for (int i = 0; i < kDSlots; ++i)
-    e[i] = i < used_slots ? stage[i * kBinBlock + tid] : make_uint2(kInvalid, 0u);
+    e[i] = i < used_slots ? stage[i * kDBlock + tid] : make_uint2(kInvalid, 0u);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kDSlots; ++i) {
@@ -214,26 +224,26 @@ __device__ inline void flush_depth_chunk(uint2 *stage, uint32_t *cnt, uint32_t *
     }
   }
   __syncthreads();
-  for (uint32_t i = tid; i < total; i += kBinBlock) {
+  for (uint32_t i = tid; i < total; i += kDBlock) {
     const uint2 v = stage[i];
     const uint32_t off = v.x & (kDTileElems - 1);
     const uint32_t k = v.x >> 24;
     ba.drecords[static_cast<size_t>(base) + i] = make_uint2(off | (k << kDTileBits), v.y);
   }
-  for (uint32_t t = tid; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
+  for (uint32_t t = tid; t < ba.n_tiles; t += kDBlock) cnt[t] = 0u;
   __syncthreads();
 }
 
-// One block of kBinBlock points of a 3D run with the twist/camera transform
+// One block of kDBlock points of a 3D run with the twist/camera transform
 // and the binned depth splat (same arithmetic as the direct depth path).
-template <typename real, int SEL>
+template <typename real, int SEL, int LIN = kLinGeneral>
 __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_maps, int n_search,
                                   const Window &win, const RunArgs &ra,
                                   const float *fparams, float near_plane, const BinArgs &ba,
                                   const Outputs &out, uint32_t block, uint2 *stage, uint32_t *cnt,
-                                  uint32_t *wsum) {
+                                  uint32_t *wsum, const SharedLinear<real, 3> &A = {}) {
   const int tid = threadIdx.x;
-  const uint32_t n = block * kBinBlock + tid;
+  const uint32_t n = block * kDBlock + tid;
   const bool active = n < ra.n_points;
   const uint32_t pid = ra.point_offset + (active ? n : 0u);
   const uint32_t T = ra.n_iters, B = ra.burn_in;
@@ -252,7 +262,10 @@ __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_m
       k = select_index<SEL>(word_of(blk, j), th, n_maps, n_search);
       if (active && out.indices)
         out.indices[static_cast<size_t>(n) * T + (t - 1)] = static_cast<uint8_t>(k);
-      apply_map<real, 3>(table, k, p);
+      if constexpr (LIN != kLinGeneral)
+        apply_shared_map<real, 3, LIN>(table, A, k, p);
+      else
+        apply_map<real, 3>(table, k, p);
       if (t > B) {
         uint2 e = make_uint2(kInvalid, 0u);
         if (active) {
@@ -268,7 +281,7 @@ __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_m
           else
             ++dropped;
         }
-        stage[slot * kBinBlock + tid] = e;
+        stage[slot * kDBlock + tid] = e;
         if (e.x != kInvalid) atomicAdd(&cnt[(e.x & 0xFFFFFFu) >> kDTileBits], 1u);
         if (++slot == kDSlots) {
           flush_depth_chunk(stage, cnt, wsum, slot, chunk, ba);

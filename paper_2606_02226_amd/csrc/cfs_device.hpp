@@ -168,17 +168,68 @@ __device__ __forceinline__ void apply_map(const real *__restrict__ table, int k,
   }
 }
 
+// Systems whose maps all share one linear part A (the similarity maps of the
+// Sierpinski triangle, the square and the Menger sponge): A is uniform over
+// the workgroup and kept in registers, and only the translation b_k is
+// gathered from LDS by the drawn index (a third or a quarter of the bytes of
+// a whole row).  With A = s I (kLinScalar) the map is one FMA per
+// coordinate, fma(s, p_i, b_i): the general map's FMAs with the zero
+// entries add exact zeros, so the result is the same (the host takes this
+// form only without negative-zero translations, whose sign the zero
+// products could change).
+template <typename real, int DIM>
+struct SharedLinear {
+  real a[DIM * DIM];
+};
+
+template <typename real, int DIM>
+__device__ __forceinline__ SharedLinear<real, DIM> shared_linear(const MapTable<DIM> &mt) {
+  SharedLinear<real, DIM> A;
+#pragma unroll
+  for (int i = 0; i < DIM * DIM; ++i) A.a[i] = static_cast<real>(mt.coef[i]);
+  return A;
+}
+
+template <typename real, int DIM, int LIN>
+__device__ __forceinline__ void apply_shared_map(const real *__restrict__ btab,
+                                                 const SharedLinear<real, DIM> &A, int k,
+                                                 real p[DIM]) {
+  const real *b = btab + k * BRowStride<DIM>::value;
+  if constexpr (LIN == kLinScalar) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) p[c] = fma(A.a[0], p[c], b[c]);
+  } else if constexpr (DIM == 2) {
+    const real x = p[0], y = p[1];
+    p[0] = fma(A.a[0], x, fma(A.a[1], y, b[0]));
+    p[1] = fma(A.a[2], x, fma(A.a[3], y, b[1]));
+  } else {
+    const real x = p[0], y = p[1], z = p[2];
+    p[0] = fma(A.a[0], x, fma(A.a[1], y, fma(A.a[2], z, b[0])));
+    p[1] = fma(A.a[3], x, fma(A.a[4], y, fma(A.a[5], z, b[1])));
+    p[2] = fma(A.a[6], x, fma(A.a[7], y, fma(A.a[8], z, b[2])));
+  }
+}
+
 __device__ inline void load_sincos_table();
 
 // Copy the kernel-argument map table into LDS rows of type `real`, the
 // selection thresholds and their guide; FP64 kernels (TRIG) also fill the
 // sine/cosine table of sincos_f64.
-template <typename real, int DIM, bool TRIG = (sizeof(real) == sizeof(double))>
+// SHARED: the translations-only table of a shared-linear-part system
+// (BRowStride values per map) instead of whole rows.
+template <typename real, int DIM, bool TRIG = (sizeof(real) == sizeof(double)), bool SHARED = false>
 __device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
                                            uint32_t *th) {
   constexpr int S = RowStride<real, DIM>::value;
   constexpr int C = DIM * (DIM + 1);
-  for (int i = threadIdx.x; i < mt.n_maps * S; i += blockDim.x) {
+  if constexpr (SHARED) {
+    constexpr int BS = BRowStride<DIM>::value;
+    for (int i = threadIdx.x; i < mt.n_maps * BS; i += blockDim.x) {
+      const int m = i / BS, c = i % BS;
+      table[i] = c < DIM ? static_cast<real>(mt.coef[m * C + DIM * DIM + c]) : static_cast<real>(0);
+    }
+  }
+  for (int i = threadIdx.x; !SHARED && i < mt.n_maps * S; i += blockDim.x) {
     const int m = i / S, c = i % S;
     real v = static_cast<real>(0);
     if constexpr (DIM == 2) {

@@ -37,6 +37,22 @@ struct MapTable {
   int32_t n_search;
   int32_t flags;     // kFlagCircle | kFlagReuse (uniform per system)
   uint64_t circle_mask;  // bit m: map m is a circle map
+  int32_t lin;  // kLinGeneral, or every map shares map 0's linear part: kLinShared, kLinScalar
+};
+
+// Linear parts of a system's maps: one per map (kLinGeneral); one for all
+// maps, bit for bit (kLinShared); one for all maps and a multiple s I of the
+// identity (kLinScalar: similarity maps without rotation, such as the
+// Sierpinski triangle's, the square's and the Menger sponge's).
+constexpr int kLinGeneral = 0;
+constexpr int kLinShared = 1;
+constexpr int kLinScalar = 2;
+
+// Rows of the translations-only LDS table of a system whose maps share one
+// linear part: b of each map, padded to 16-byte reads.
+template <int DIM>
+struct BRowStride {
+  static constexpr int value = (DIM == 2) ? 2 : 4;
 };
 
 struct Window {
@@ -72,11 +88,14 @@ constexpr int kAccBlock = 1024;  // two per CU: 8 waves per SIMD
 
 // Binned depth splat: records are (pixel | index << 24, FP32 depth bits),
 // kDSlots per lane per chunk, sorted by tiles of kDTileElems pixels whose
-// u64 keys and u32 counts fit in LDS together.  Sixteen slots: the 64 KB
-// stage, the tile counts and a 20-map FP64 table keep two chaos workgroups
-// per CU, and a run of 16 splatted steps per point fills one whole chunk.
+// u64 keys and u32 counts fit in LDS together.  One 1024-lane workgroup per
+// CU with a 128 KB stage: 16384 records per chunk, so that each chunk's run
+// of a tile is long (the accumulate reads runs scattered over the records,
+// and longer runs fetch fewer partly used cache lines); sixteen slots hold a
+// run of 16 splatted steps per point in one chunk.
+constexpr int kDBlock = 1024;
 constexpr int kDSlots = 16;
-constexpr uint32_t kDCap = static_cast<uint32_t>(kBinBlock) * kDSlots;
+constexpr uint32_t kDCap = static_cast<uint32_t>(kDBlock) * kDSlots;
 constexpr int kDTileBits = 13;
 constexpr uint32_t kDTileElems = 1u << kDTileBits;
 constexpr int kDAccBlock = 1024;  // one per CU (96 KB of LDS): 4 waves per SIMD

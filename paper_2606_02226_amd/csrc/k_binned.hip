@@ -18,7 +18,7 @@
 
 namespace cfs {
 
-template <typename real, int DIM, int FINAL, bool EQUAL, bool GENERAL>
+template <typename real, int DIM, int FINAL, bool EQUAL, bool GENERAL, int LIN>
 __global__ __launch_bounds__(kBinBlock) void k_chaos_binned(MapTable<DIM> mt, Window win,
                                                             RunArgs ra, FinalArgs fa, BinArgs ba,
                                                             Outputs out) {
@@ -27,18 +27,20 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_binned(MapTable<DIM> mt, Wi
   __shared__ uint32_t stage[kChunkCap];
   __shared__ uint32_t cnt[kMaxTiles];
   __shared__ uint32_t wsum[kWaves + 1];
-  load_table<real, DIM>(mt, table, th);
+  load_table<real, DIM, sizeof(real) == sizeof(double), LIN != kLinGeneral>(mt, table, th);
   for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
   __syncthreads();
-  chaos_binned_block<real, DIM, FINAL, EQUAL, GENERAL>(table, th, mt.n_maps, mt.n_search,
-                                                       mt.flags, win, ra, fa.p, ba,
-                                                       out, blockIdx.x, stage, cnt, wsum);
+  chaos_binned_block<real, DIM, FINAL, EQUAL, GENERAL, LIN>(
+      table, th, mt.n_maps, mt.n_search, mt.flags, win, ra, fa.p, ba, out, blockIdx.x, stage, cnt,
+      wsum, shared_linear<real, DIM>(mt));
 }
 
 // The map table sits in dynamic LDS sized for the system's own maps, so that
 // the 64 KB stage leaves room for two workgroups per CU.
-template <typename real, bool EQUAL>
-__global__ __launch_bounds__(kBinBlock) void k_chaos_depth_binned(MapTable<3> mt, Window win,
+// One 1024-lane workgroup per CU (the 128 KB stage): four waves per SIMD,
+// 128 VGPRs.
+template <typename real, bool EQUAL, int LIN>
+__global__ __launch_bounds__(kDBlock) void k_chaos_depth_binned(MapTable<3> mt, Window win,
                                                                   RunArgs ra, FinalArgs fa,
                                                                   float near_plane, BinArgs ba,
                                                                   Outputs out) {
@@ -47,13 +49,13 @@ __global__ __launch_bounds__(kBinBlock) void k_chaos_depth_binned(MapTable<3> mt
   __shared__ uint32_t th[kThWords];
   __shared__ uint2 stage[kDCap];
   __shared__ uint32_t cnt[kMaxTiles];
-  __shared__ uint32_t wsum[kWaves + 1];
-  load_table<real, 3>(mt, table, th);
-  for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kBinBlock) cnt[t] = 0u;
+  __shared__ uint32_t wsum[kDWaves + 1];
+  load_table<real, 3, sizeof(real) == sizeof(double), LIN != kLinGeneral>(mt, table, th);
+  for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kDBlock) cnt[t] = 0u;
   __syncthreads();
-  chaos_depth_block<real, EQUAL ? kSelEqual : kSelTable>(table, th, mt.n_maps, mt.n_search,
-                                                         win, ra, fa.p, near_plane,
-                                                         ba, out, blockIdx.x, stage, cnt, wsum);
+  chaos_depth_block<real, EQUAL ? kSelEqual : kSelTable, LIN>(
+      table, th, mt.n_maps, mt.n_search, win, ra, fa.p, near_plane, ba, out, blockIdx.x, stage,
+      cnt, wsum, shared_linear<real, 3>(mt));
 }
 
 // Record total of tile t over all chunks, from the transpose's column sums
@@ -167,7 +169,8 @@ BinPlan bin_plan(uint32_t points, uint32_t n_iters, uint32_t burn_in, uint32_t e
                  uint32_t per_iter) {
   BinPlan bp{};
   const uint32_t slots = depth ? kDSlots : kBinSlots;
-  bp.blocks = (points + kBinBlock - 1) / kBinBlock;
+  const uint32_t block = depth ? kDBlock : kBinBlock;
+  bp.blocks = (points + block - 1) / block;
   bp.flushes = ((n_iters - burn_in) * per_iter + slots - 1) / slots;
   bp.n_chunks = bp.blocks * bp.flushes;
   bp.n_tiles = depth ? (elems + kDTileElems - 1) / kDTileElems : (elems + kTileElems - 1) / kTileElems;
@@ -204,12 +207,19 @@ static hipError_t launch_binned_typed(const ChaosJob &j, hipStream_t s) {
   const uint32_t blocks = (j.ra.n_points + kBinBlock - 1) / kBinBlock;
   mark_phase(j.ev, 0, s);
   // circle maps, reuse composition (2D only) and continued runs take the
-  // general variant
+  // general variant; systems whose maps share one linear part gather only
+  // the translations
   if (mt.flags != 0 || j.ra.iter_block != 0)
-    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, true>), dim3(blocks),
+    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, true, kLinGeneral>), dim3(blocks),
+                       dim3(kBinBlock), 0, s, mt, j.win, j.ra, j.fa, j.ba, j.out);
+  else if (mt.lin == kLinScalar)
+    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, false, kLinScalar>), dim3(blocks),
+                       dim3(kBinBlock), 0, s, mt, j.win, j.ra, j.fa, j.ba, j.out);
+  else if (mt.lin == kLinShared)
+    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, false, kLinShared>), dim3(blocks),
                        dim3(kBinBlock), 0, s, mt, j.win, j.ra, j.fa, j.ba, j.out);
   else
-    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, false>), dim3(blocks),
+    hipLaunchKernelGGL((k_chaos_binned<real, DIM, FINAL, EQUAL, false, kLinGeneral>), dim3(blocks),
                        dim3(kBinBlock), 0, s, mt, j.win, j.ra, j.fa, j.ba, j.out);
   hipError_t e = hipGetLastError();
   mark_phase(j.ev, 1, s);
@@ -241,15 +251,25 @@ static hipError_t launch_binned_real(const ChaosJob &j, hipStream_t s) {
 
 template <typename real>
 static hipError_t launch_depth_binned(const ChaosJob &j, hipStream_t s) {
-  const uint32_t blocks = (j.ra.n_points + kBinBlock - 1) / kBinBlock;
-  const size_t table_bytes = static_cast<size_t>(j.mt3.n_maps) * RowStride<real, 3>::value * sizeof(real);
+  const uint32_t blocks = (j.ra.n_points + kDBlock - 1) / kDBlock;
+  const int lin = j.mt3.lin;
+  const size_t table_bytes =
+      static_cast<size_t>(j.mt3.n_maps) *
+      (lin != kLinGeneral ? BRowStride<3>::value : RowStride<real, 3>::value) * sizeof(real);
   mark_phase(j.ev, 0, s);
-  if (j.equal)
-    hipLaunchKernelGGL((k_chaos_depth_binned<real, true>), dim3(blocks), dim3(kBinBlock),
-                       table_bytes, s, j.mt3, j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
-  else
-    hipLaunchKernelGGL((k_chaos_depth_binned<real, false>), dim3(blocks), dim3(kBinBlock),
-                       table_bytes, s, j.mt3, j.win, j.ra, j.fa, j.near_plane, j.ba, j.out);
+#define CFS_DEPTH_LAUNCH(EQ, LN)                                                               \
+  hipLaunchKernelGGL((k_chaos_depth_binned<real, EQ, LN>), dim3(blocks), dim3(kDBlock),        \
+                     table_bytes, s, j.mt3, j.win, j.ra, j.fa, j.near_plane, j.ba, j.out)
+  if (j.equal) {
+    if (lin == kLinScalar) CFS_DEPTH_LAUNCH(true, kLinScalar);
+    else if (lin == kLinShared) CFS_DEPTH_LAUNCH(true, kLinShared);
+    else CFS_DEPTH_LAUNCH(true, kLinGeneral);
+  } else {
+    if (lin == kLinScalar) CFS_DEPTH_LAUNCH(false, kLinScalar);
+    else if (lin == kLinShared) CFS_DEPTH_LAUNCH(false, kLinShared);
+    else CFS_DEPTH_LAUNCH(false, kLinGeneral);
+  }
+#undef CFS_DEPTH_LAUNCH
   hipError_t e = hipGetLastError();
   mark_phase(j.ev, 1, s);
   if (e == hipSuccess && j.ba.n_chunks != 0)

@@ -26,7 +26,7 @@ def _lib():
 
 def test_refuses_runs_beyond_the_scratch():
     """A depth run with 70000 splatted steps per point: one workgroup's 8-byte
-    records alone (4375 chunks of 8192) take 287 MB, more than the 256 MiB
+    records alone (4375 chunks of 16384) take 573 MB, more than the 256 MiB
     array, while they fit cfs_chaos_game's launch budget (2^28 records).  BINNED is
     refused before anything is enqueued; nothing is dereferenced."""
     L = _lib()
