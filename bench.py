@@ -21,6 +21,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -124,7 +125,11 @@ def _pmc_rows(directory, counter):
 def _workload(name):
     import workloads
     return {"menger": workloads.menger, "cfs_square": workloads.cfs_square,
-            "sierpinski": workloads.sierpinski}[name]()
+            "sierpinski": workloads.sierpinski,
+            # the paper's circle primitive alone, and mixed with two affine
+            # maps (the kernels then sort points by the kind of map drawn)
+            "circle": lambda: workloads.circle(n_points=1 << 22),
+            "circle_mixed": lambda: workloads.circle(n_points=1 << 22, extra_affine=2)}[name]()
 
 
 # kernels of each configuration's step, as (name fragment, key)
@@ -134,6 +139,10 @@ STEP_KERNELS = {
     "cfs_square": (("k_chaos_binned", "chaos_kernel"), ("k_transpose", "table_transpose"),
                    ("k_tile_accumulate", "tile_accumulate"), ("k_fill", "image_clear")),
     "sierpinski": (("k_chaos", "chaos_kernel"), ("k_fill", "image_clear")),
+    "circle": (("k_chaos_binned", "chaos_kernel"), ("k_transpose", "table_transpose"),
+               ("k_tile_accumulate", "tile_accumulate"), ("k_fill", "image_clear")),
+    "circle_mixed": (("k_chaos_binned", "chaos_kernel"), ("k_transpose", "table_transpose"),
+                     ("k_tile_accumulate", "tile_accumulate"), ("k_fill", "image_clear")),
 }
 
 
@@ -164,6 +173,77 @@ def summarise_valu(directory, workload, precision):
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    paths = sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True))
+    if not paths:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    with open(paths[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarise_trace(directory, log_path, workload, precision, steps=5, warmup=2):
+    """Write profiles/trace_<workload>_<precision>.md from a rocprofv3
+    --kernel-trace --stats run of this benchmark (--steps 5 --warmup 2) and
+    the JSON line that run printed (log_path): the kernel statistics, the
+    registers and LDS of each kernel, and the roofline kernel's mean over
+    the timed steps' launches beside the bench line's own HIP-event figure,
+    with the fraction that the profiled mean gives."""
+    line = None
+    with open(log_path) as fh:
+        for text in fh:
+            if text.startswith('{"metric"'):
+                line = json.loads(text)
+    if line is None:
+        raise SystemExit(f"no bench line in {log_path}")
+    stats = _csv_rows(directory, "_kernel_stats.csv")
+    trace = _csv_rows(directory, "_kernel_trace.csv")
+    frag = STEP_KERNELS[workload][0][0]
+    mine = [r for r in trace if frag + "<" in r["Kernel_Name"]]
+    mine.sort(key=lambda r: int(r["Start_Timestamp"]))
+    per_step = len(mine) // (steps + warmup)
+    timed = mine[warmup * per_step:]
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in timed]
+    step_ms = float(np.sum(dur)) / steps
+    roof = line["roofline"]
+    frac = roof["lane_ops_per_step"] / (step_ms * 1e-3) / 1e12 / roof["peak"]
+    res = {}
+    for r in trace:
+        name = r["Kernel_Name"]
+        res.setdefault(name, (r["VGPR_Count"], r["Accum_VGPR_Count"], r["SGPR_Count"],
+                              r["LDS_Block_Size"], r["Scratch_Size"], r["Workgroup_Size_X"]))
+    out = [f"# Kernel trace -- {workload}, {precision.upper()} positions", "",
+           f"Workload: {line['config']['workload']}.  One MI355X.", "",
+           "Command (repository root; `DIR` is an output folder):", "", "```",
+           "cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv \\",
+           f"    -d DIR -o {workload} -- python3 bench.py --workload {workload} --precision {precision} \\",
+           f"    --steps {steps} --warmup {warmup} --no-cpu-baseline --no-forms --no-configs --no-ceilings",
+           "```", "",
+           f"Kernel statistics ({steps + warmup} steps: {warmup} warm-up + {steps} timed):", "",
+           "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share | VGPR | AGPR | SGPR | LDS (B) | Scratch (B) | Lanes |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in stats:
+        name = r["Name"]
+        short = name.split("(")[0].replace("void ", "")
+        v = res.get(name, ("", "", "", "", "", ""))
+        out.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.1f}% | " + " | ".join(v) + " |")
+    out += ["", f"The roofline kernel (`{frag}`): {per_step} launch(es) per step; over the "
+            f"{steps} timed steps {step_ms:.3f} ms per step in the trace, against "
+            f"{line['phase_ms']['chaos_kernel']:.3f} ms from the library's HIP events in the "
+            f"bench line of the same run ({line['ms_per_step']:.3f} ms per step under the "
+            f"profiler).  Fraction of the VALU model from the trace: "
+            f"{roof['lane_ops_per_step']:.4g} lane-ops / {step_ms:.3f} ms / "
+            f"{roof['peak']:.2f} T = **{frac:.3f}** (the line: {roof['frac']:.3f}).", ""]
+    out += ["Phases of the bench line (ms per step): " +
+            ", ".join(f"{k} {v:.3f}" for k, v in line["phase_ms"].items()) + ".", ""]
+    path = os.path.join(ROOT, "profiles", f"trace_{workload}_{precision}.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out))
+    print("\n".join(out))
 
 
 def summarise_pmc(fetch_dir, write_dir, workload, precision):
@@ -614,7 +694,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["menger", "cfs_square", "sierpinski"],
+    ap.add_argument("--workload", choices=["menger", "cfs_square", "sierpinski", "circle",
+                                           "circle_mixed"],
                     default="menger", help="the headline configuration")
     ap.add_argument("--precision", choices=["f32", "f64"], default=None,
                     help="positions (default: f64, f32 for the Sierpinski triangle)")
@@ -631,14 +712,20 @@ def main():
     ap.add_argument("--summarise-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_<workload>_<precision>.json from two "
                          "rocprofv3 --pmc output folders and exit (no GPU needed)")
+    ap.add_argument("--summarise-trace", nargs=2, metavar=("TRACE_DIR", "LOG"),
+                    help="write profiles/trace_<workload>_<precision>.md from a rocprofv3 "
+                         "--kernel-trace --stats run (--steps 5 --warmup 2) and its output")
     ap.add_argument("--summarise-valu", metavar="VALU_DIR",
                     help="write profiles/valu_<workload>_<precision>.json from a rocprofv3 "
                          "--pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVES output folder and "
                          "exit (no GPU needed)")
     args = ap.parse_args()
-    default_prec = {"menger": "f64", "cfs_square": "f64", "sierpinski": "f32"}
+    default_prec = {"menger": "f64", "cfs_square": "f64", "sierpinski": "f32", "circle": "f64",
+                    "circle_mixed": "f64"}
     precision = args.precision or default_prec[args.workload]
-    if args.summarise_pmc or args.summarise_valu:
+    if args.summarise_pmc or args.summarise_valu or args.summarise_trace:
+        if args.summarise_trace:
+            summarise_trace(*args.summarise_trace, args.workload, precision)
         if args.summarise_pmc:
             summarise_pmc(*args.summarise_pmc, args.workload, precision)
         if args.summarise_valu:
@@ -658,8 +745,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ceil = None if args.no_ceilings else ceilings(dev)
-    sample_log2 = args.cpu_sample_log2 or {"menger": 22, "cfs_square": 23, "sierpinski": 16}[
-        args.workload]
+    sample_log2 = args.cpu_sample_log2 or {"menger": 22, "cfs_square": 23, "sierpinski": 16,
+                                            "circle": 18, "circle_mixed": 18}[args.workload]
     head = chaos_leg(args.workload, dev, args.steps, args.warmup, precision, args.splat_path,
                      ceil, error=not args.no_cpu_baseline, cpu=not args.no_cpu_baseline,
                      cpu_sample_log2=sample_log2, calibration_copy=args.calibration_copy)
@@ -694,7 +781,11 @@ def main():
             "cfs_square": "cfs_square: 4-map square + swirl/translate copy, 4-channel u32 "
                           "2048x2048, 2^24 points x 32 iterations (8 burn-in)",
             "sierpinski": "sierpinski: 3 maps, 512x512 u32, 2^16 points x 64 iterations "
-                          "(16 burn-in)"}[args.workload],
+                          "(16 burn-in)",
+            "circle": "circle: the paper's circle IFS (2 circle maps), 2x512x512 u32, 2^22 "
+                      "points x 48 iterations (16 burn-in)",
+            "circle_mixed": "circle_mixed: 2 circle maps + 2 affine maps, 4x512x512 u32, 2^22 "
+                            "points x 48 iterations (16 burn-in)"}[args.workload],
             "points": head["points"], "iterations": head["iterations"],
             "burn_in": head["burn_in"], "image": head["image"], "precision": precision},
         "roofline": roof,

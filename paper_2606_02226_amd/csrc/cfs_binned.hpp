@@ -186,6 +186,9 @@ __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_
   }
   if (slot > 0) flush_chunk(stage, cnt, wsum, slot, chunk, ba);
 
+  if (out.dropped && dropped)
+    __hip_atomic_fetch_add(out.dropped, static_cast<unsigned long long>(dropped),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!active) return;
   if (out.final_points) {
     real *fp = static_cast<real *>(out.final_points) + static_cast<size_t>(n) * DIM;
@@ -193,9 +196,6 @@ __device__ void chaos_binned_block(const real *table, const uint32_t *th, int n_
     for (int c = 0; c < DIM; ++c) fp[c] = p[c];
   }
   if (out.last_index) out.last_index[n] = static_cast<uint8_t>(k);
-  if (out.dropped && dropped)
-    __hip_atomic_fetch_add(out.dropped, static_cast<unsigned long long>(dropped),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,12 +310,13 @@ __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_m
 // are walked by groups of 2^log2g lanes, each lane loading two records per
 // 16-byte load from the even record at or below the run start (records
 // outside [start, end) are skipped; a chunk holds an even number of records,
-// so no load leaves it), kDRunsInFlight runs per group at a time.  The
-// kernel waits on memory, so the run bounds of the next round are loaded
-// while the current round's records are counted, and every lane keeps
-// kDRunsInFlight record loads in flight.  Every thread calls it; keys and
-// counts are kDTileElems each.
-constexpr int kDRunsInFlight = 8;
+// so no load leaves it), kDRunsInFlight runs per group per round.  The
+// kernel waits on memory: while a round's records are counted, the records
+// of the next kDAhead rounds are in flight and the run bounds of the round
+// after them are loading.  Every thread calls it; keys and counts are
+// kDTileElems each.
+constexpr int kDRunsInFlight = 4;
+constexpr int kDAhead = 1;
 static_assert(kDCap % 2 == 0, "depth chunks hold whole 16-byte record pairs");
 
 __device__ __forceinline__ void depth_record(unsigned long long *keys, uint32_t *counts,
@@ -366,29 +367,50 @@ __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
   const uint32_t g = 1u << log2g, lane = tid & (g - 1u);
   const uint32_t groups = kDAccBlock >> log2g;
   const uint32_t round = groups * kDRunsInFlight;
-  uint32_t s[kDRunsInFlight], e[kDRunsInFlight];
-  depth_run_bounds(row0, row1, tid >> log2g, groups, n_chunks, s, e);
-  for (uint32_t c0 = tid >> log2g; c0 < n_chunks; c0 += round) {
-    uint4 v[kDRunsInFlight];
+  // ring of kDAhead + 1 rounds: bounds of rounds i .. i + kDAhead, records
+  // of rounds i .. i + kDAhead - 1 issued before the loop turn of round i
+  constexpr int D = kDAhead;
+  uint32_t s[D + 1][kDRunsInFlight], e[D + 1][kDRunsInFlight];
+  uint4 v[D + 1][kDRunsInFlight];
+  const uint32_t first = tid >> log2g;
+#pragma unroll
+  for (int r = 0; r <= D; ++r) depth_run_bounds(row0, row1, first + r * round, groups, n_chunks, s[r], e[r]);
+#pragma unroll
+  for (int r = 0; r < D; ++r)
 #pragma unroll
     for (int u = 0; u < kDRunsInFlight; ++u) {
-      const uint32_t i = (s[u] & ~1u) + 2u * lane;
-      v[u] = i < e[u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
+      const uint32_t i = (s[r][u] & ~1u) + 2u * lane;
+      v[r][u] = i < e[r][u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
     }
-    // the next round's bounds, loaded while this round's records arrive
-    uint32_t s2[kDRunsInFlight], e2[kDRunsInFlight];
-    depth_run_bounds(row0, row1, c0 + round, groups, n_chunks, s2, e2);
+  for (uint32_t c0 = first; c0 < n_chunks; c0 += round) {
+    // round i + D: its records, and the bounds of the round after it
 #pragma unroll
     for (int u = 0; u < kDRunsInFlight; ++u) {
-      const uint32_t i = (s[u] & ~1u) + 2u * lane;
-      depth_pair(keys, counts, v[u], i, s[u], e[u]);
-      for (uint32_t j = i + 2u * g; j < e[u]; j += 2u * g)
-        depth_pair(keys, counts, *reinterpret_cast<const uint4 *>(rec + j), j, s[u], e[u]);
+      const uint32_t i = (s[D][u] & ~1u) + 2u * lane;
+      v[D][u] = i < e[D][u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    uint32_t sn[kDRunsInFlight], en[kDRunsInFlight];
+    depth_run_bounds(row0, row1, c0 + (D + 1) * round, groups, n_chunks, sn, en);
+    // round i: count its records
+#pragma unroll
+    for (int u = 0; u < kDRunsInFlight; ++u) {
+      const uint32_t i = (s[0][u] & ~1u) + 2u * lane;
+      depth_pair(keys, counts, v[0][u], i, s[0][u], e[0][u]);
+      for (uint32_t j = i + 2u * g; j < e[0][u]; j += 2u * g)
+        depth_pair(keys, counts, *reinterpret_cast<const uint4 *>(rec + j), j, s[0][u], e[0][u]);
     }
 #pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int u = 0; u < kDRunsInFlight; ++u) {
+        v[r][u] = v[r + 1][u];
+        s[r][u] = s[r + 1][u];
+        e[r][u] = e[r + 1][u];
+      }
+#pragma unroll
     for (int u = 0; u < kDRunsInFlight; ++u) {
-      s[u] = s2[u];
-      e[u] = e2[u];
+      s[D][u] = sn[u];
+      e[D][u] = en[u];
     }
   }
   __syncthreads();

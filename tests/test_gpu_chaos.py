@@ -282,6 +282,22 @@ def test_binned_drops_and_ragged(api, orc):
     assert got["dropped"] == ref["dropped"] > 0
 
 
+@pytest.mark.parametrize("shape", [(300, 170), (128, 129), (40, 700)])
+def test_binned_per_index_channels_ragged(api, orc, shape):
+    """Per-index counts (one channel per map) in images whose planes are not
+    multiples of the binned splat's 16384-element tiles, so tiles straddle
+    two channels' planes and the last one lies partly past the image; the
+    image equals the oracle's."""
+    W_, H_ = shape
+    w = W.sierpinski(n_points=(1 << 15) + 7, n_iters=29, burn_in=5)
+    image = {"kind": "u32_count", "width": W_, "height": H_, "channels": 3,
+             "lo": [-0.05, -0.05], "hi": [1.05, 0.95]}
+    got = _image_of(api, w, "f64", "binned", image=image)
+    ref = orc.chaos_count(w["system"], w["run"], image)
+    assert np.array_equal(got["image"], ref["image"])
+    assert got["dropped"] == ref["dropped"]
+
+
 def test_binned_concentrated_and_empty_tiles(api):
     # the attractor covers 64x64 pixels of a 4096x4096 image: 16 of 1024 tiles
     # hold every record (runs of ~770 records: several passes of the widest
@@ -509,6 +525,27 @@ def test_depth_binned_equals_direct(api, precision):
     assert a["dropped"] == b["dropped"]
 
 
+@pytest.mark.parametrize("shape", [(1000, 700), (200, 90), (130, 1000), (64, 64)])
+def test_depth_ragged_tiles_vs_oracle(api, orc, shape):
+    """Depth images whose last 8192-pixel tile of the binned splat lies
+    partly past the image (and one image smaller than a tile), at other
+    aspect ratios than the square workloads.  Binned keys and density equal
+    the direct splat's bit for bit, and the oracle's."""
+    W_, H_ = shape
+    w = W.menger(n_points=(1 << 14) + 5, side=1024)
+    w["image"] = dict(w["image"], width=W_, height=H_)
+    got = _depth_image(api, w, "f64", "binned")
+    direct = _depth_image(api, w, "f64", "direct")
+    assert np.array_equal(got["depth"], direct["depth"])
+    assert np.array_equal(got["density"], direct["density"])
+    assert got["dropped"] == direct["dropped"]
+    ref = orc.chaos_depth(w["system"], w["run"], w["image"], w["image"]["near"])
+    assert got["dropped"] == ref["dropped"]
+    assert np.array_equal(got["density"], ref["density"])
+    occupied, differ, occ_diff, ulps = depth_key_diff(got["depth"], ref["depth"])
+    assert occ_diff == 0 and differ == 0, (differ, ulps)
+
+
 def test_depth_binned_vs_oracle(api, orc):
     w = W.menger(n_points=1 << 14, side=1024)
     got = _depth_image(api, w, "f64", "binned")
@@ -617,15 +654,35 @@ def test_circle_fp32_indices_and_measure(api, orc):
     assert np.all(u <= 1.0 + 1e-6) and abs(u.mean() - 0.5) < 5 * math.sqrt(1 / 12 / u.size)
 
 
+@pytest.mark.parametrize("compose", ["copy", "reuse"])
 @pytest.mark.parametrize("path", ["direct", "binned"])
-def test_mixed_kinds_parity(api, orc, path):
-    # two circle maps and two affine maps in one system: waves hold both kinds
+def test_mixed_kinds_parity(api, orc, path, compose):
+    """Two circle maps and two affine maps in one system, so waves hold both
+    kinds at once: every point's index sequence and last index are the
+    oracle's bit for bit, its final position within rounding, the image
+    within the histogram bar, and a ragged last workgroup (20000 points) and
+    dropped splats are accounted for."""
     w = W.circle(n_points=20000, extra_affine=2)
+    if compose == "reuse":
+        w = dict(w, system=dict(w["system"], final_kind="swirl",
+                                final_params=np.array([0, 0, 1.5, 0, 0] + [0] * 19, np.float32),
+                                compose="reuse"))
+    N, T = w["run"]["n_points"], w["run"]["n_iters"]
     img = api.Image(w["image"], device=_dev()).clear()
-    api.chaos_game(w["system"], w["run"], img, precision="f64", splat_path=path)
+    fin = torch.empty((N, 2), dtype=torch.float64, device=_dev())
+    last = torch.empty((N,), dtype=torch.uint8, device=_dev())
+    idx = torch.empty((N, T), dtype=torch.uint8, device=_dev())
+    api.chaos_game(w["system"], w["run"], img, precision="f64", splat_path=path, final=fin,
+                   last=last, indices=idx)
     got = img.to_numpy()
-    ref = orc.chaos_count(w["system"], w["run"], w["image"])
+    ref = orc.chaos_count(w["system"], w["run"], w["image"], want_final=True, want_last=True,
+                          want_indices=True)
+    assert np.array_equal(idx.cpu().numpy(), ref["indices"])
+    assert np.array_equal(last.cpu().numpy(), ref["last"])
+    assert got["dropped"] == ref["dropped"]
     assert rel_l1(got["image"], ref["image"]) <= 1e-4
+    # positions: within rounding, except near the circle maps' singular set
+    _check_circle_positions(orc, w, {"final": fin.cpu().numpy()}, ref, 1e-9, 1e-6)
 
 
 @pytest.mark.parametrize("path", ["direct", "binned"])
