@@ -417,6 +417,16 @@ def ceilings(dev):
         rate = n / (ms * 1e-3)
         out[kind] = {"G_per_s": rate / 1e9, "per_cu_per_clock": rate / (N_CU * CLOCK_HZ),
                      "what": what}
+    # scattered runs in 2 GiB (beyond the caches), the accumulates' pattern
+    rbuf = torch.zeros((4 << 20) + (2 << 30), dtype=torch.uint8, device=dev)
+    for kind, length in (("runs_128", 128), ("runs_512", 512), ("runs_2048", 2048)):
+        ops = (1 << 31) // length
+        n = api.microbench(kind, rbuf, ops=ops)
+        ms = _timed(lambda: api.microbench(kind, rbuf, ops=ops), 3, stream)
+        out[kind] = {"GB_per_s": n / (ms * 1e-3) / 1e9, "bytes": n,
+                     "what": f"reads of {length}-byte runs at random 16-byte-aligned places "
+                             "in 2 GiB"}
+    del rbuf
     lanes = 4096 * 256
     pbuf = torch.zeros(lanes * 4, dtype=torch.uint8, device=dev)
     n = api.microbench("philox", pbuf, ops=lanes * 256)
@@ -465,8 +475,14 @@ def _phase_rooflines(name, w, ms, ceil):
                 what = "u32 add per splat"
             out["tile_accumulate"]["lds_atomic_bound_ms"] = lds_ms
             out["tile_accumulate"]["lds_atomics"] = what
-            out["tile_accumulate"]["frac_of_lower_bound"] = \
-                max(hbm_ms, lds_ms) / ms["tile_accumulate"]
+            bound = max(hbm_ms, lds_ms)
+            if "runs_128" in ceil:
+                # the records arrive as runs of 15-40 records at scattered
+                # places: the measured read rate of 128-byte runs bounds them
+                runs_ms = splats * rec / (ceil["runs_128"]["GB_per_s"] * 1e9) * 1e3
+                out["tile_accumulate"]["runs_read_bound_ms"] = runs_ms
+                bound = max(bound, runs_ms)
+            out["tile_accumulate"]["frac_of_lower_bound"] = bound / ms["tile_accumulate"]
     if ms.get("table_transpose", 0) > 0:
         out["table_transpose"] = {"ms": ms["table_transpose"]}
     for v in out.values():

@@ -473,7 +473,14 @@ int cfs_philox_dump(uint64_t seed, const uint32_t *ctrs, uint32_t *out,
  *   LDS_MIN_U64  the same with u64 atomic minima (bytes >= 4 KiB);
  *   LDS_ADD_U64  the same with u64 atomic adds (bytes >= 4 KiB);
  *   PHILOX       about `ops` Philox4x32-10 blocks (buf >= 4 MiB receives one
- *                word per lane).
+ *                word per lane);
+ *   RUNS_128, RUNS_512, RUNS_2048
+ *                about `ops` reads of runs of 128, 512 or 2048 bytes at
+ *                uniformly random 16-byte-aligned places (8, 32 or 128 lanes
+ *                per run, 16 bytes each, four runs in flight per group): the
+ *                first 4 MiB of buf receive one word per lane, the rest
+ *                holds the runs (make it larger than the caches); *done =
+ *                bytes read.
  * buf: device, 16-byte aligned, caller-owned; its contents are overwritten.
  * *done (host) receives the operations (or bytes) actually issued; the
  * caller times the call with events on `stream`.  Enqueues one kernel. */
@@ -484,7 +491,10 @@ enum {
   CFS_MB_LDS_ADD_U32 = 3,
   CFS_MB_LDS_MIN_U64 = 4,
   CFS_MB_PHILOX = 5,
-  CFS_MB_LDS_ADD_U64 = 6
+  CFS_MB_LDS_ADD_U64 = 6,
+  CFS_MB_RUNS_128 = 7,
+  CFS_MB_RUNS_512 = 8,
+  CFS_MB_RUNS_2048 = 9
 };
 int cfs_microbench(int32_t kind, void *buf, size_t bytes, uint64_t ops,
                    uint64_t *done, void *stream);

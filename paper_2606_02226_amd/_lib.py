@@ -36,7 +36,8 @@ EXPORTS = (
     "cfs_timing_enable", "cfs_timing_read", "cfs_microbench", "cfs_chaos_game_noalloc",
 )
 MICROBENCH = {"copy": 0, "dev_add_u32": 1, "dev_min_u64": 2, "lds_add_u32": 3,
-              "lds_min_u64": 4, "philox": 5, "lds_add_u64": 6}
+              "lds_min_u64": 4, "philox": 5, "lds_add_u64": 6, "runs_128": 7, "runs_512": 8,
+              "runs_2048": 9}
 
 
 class CfsSystem(C.Structure):

@@ -186,9 +186,9 @@ def chaos_game_noalloc(system, run, image, *, precision="f32", final=None, last=
 
 def microbench(kind, buf, ops=0, stream=None):
     """Enqueue one ceiling probe (cfs_microbench) over the uint8 device
-    tensor ``buf``; returns the operations (bytes for 'copy') it issues.
-    ``kind``: copy, dev_add_u32, dev_min_u64, lds_add_u32, lds_min_u64,
-    philox."""
+    tensor ``buf``; returns the operations (bytes for 'copy' and the runs)
+    it issues.  ``kind``: copy, dev_add_u32, dev_min_u64, lds_add_u32,
+    lds_add_u64, lds_min_u64, philox, runs_128, runs_512, runs_2048."""
     done = C.c_uint64(0)
     check(_lib.load().cfs_microbench(_lib.MICROBENCH[kind], _ptr(buf),
                                      C.c_size_t(buf.numel() * buf.element_size()),

@@ -239,7 +239,7 @@ __device__ inline void flush_depth_chunk(uint2 *stage, uint32_t *cnt, uint32_t *
 template <typename real, int SEL, int LIN = kLinGeneral>
 __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_maps, int n_search,
                                   const Window &win, const RunArgs &ra,
-                                  const float *fparams, float near_plane, const BinArgs &ba,
+                                  const real *fparams, float near_plane, const BinArgs &ba,
                                   const Outputs &out, uint32_t block, uint2 *stage, uint32_t *cnt,
                                   uint32_t *wsum, const SharedLinear<real, 3> &A = {}) {
   const int tid = threadIdx.x;
@@ -310,12 +310,12 @@ __device__ void chaos_depth_block(const real *table, const uint32_t *th, int n_m
 // are walked by groups of 2^log2g lanes, each lane loading two records per
 // 16-byte load from the even record at or below the run start (records
 // outside [start, end) are skipped; a chunk holds an even number of records,
-// so no load leaves it), kDRunsInFlight runs per group per round.  The
-// kernel waits on memory: while a round's records are counted, the records
-// of the next kDAhead rounds are in flight and the run bounds of the round
-// after them are loading.  Every thread calls it; keys and counts are
-// kDTileElems each.
-constexpr int kDRunsInFlight = 4;
+// so no load leaves it), kDRunsInFlight runs per group per round, kDPasses
+// loads per lane and run.  The kernel waits on memory: while a round's
+// records are counted, the records of the next kDAhead rounds are in flight
+// and the run bounds of the round after them are loading.  Every thread
+// calls it; keys and counts are kDTileElems each.
+constexpr int kDRunsInFlight = 1;
 constexpr int kDAhead = 1;
 static_assert(kDCap % 2 == 0, "depth chunks hold whole 16-byte record pairs");
 
@@ -370,40 +370,49 @@ __device__ inline void depth_tile_accumulate(const uint2 *__restrict__ rec,
   // ring of kDAhead + 1 rounds: bounds of rounds i .. i + kDAhead, records
   // of rounds i .. i + kDAhead - 1 issued before the loop turn of round i
   constexpr int D = kDAhead;
+  constexpr int P = kDPasses;
   uint32_t s[D + 1][kDRunsInFlight], e[D + 1][kDRunsInFlight];
-  uint4 v[D + 1][kDRunsInFlight];
+  uint4 v[D + 1][kDRunsInFlight][P];
   const uint32_t first = tid >> log2g;
 #pragma unroll
   for (int r = 0; r <= D; ++r) depth_run_bounds(row0, row1, first + r * round, groups, n_chunks, s[r], e[r]);
 #pragma unroll
   for (int r = 0; r < D; ++r)
 #pragma unroll
-    for (int u = 0; u < kDRunsInFlight; ++u) {
-      const uint32_t i = (s[r][u] & ~1u) + 2u * lane;
-      v[r][u] = i < e[r][u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
-    }
+    for (int u = 0; u < kDRunsInFlight; ++u)
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const uint32_t i = (s[r][u] & ~1u) + 2u * (lane + q * g);
+        v[r][u][q] = i < e[r][u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
+      }
   for (uint32_t c0 = first; c0 < n_chunks; c0 += round) {
     // round i + D: its records, and the bounds of the round after it
 #pragma unroll
-    for (int u = 0; u < kDRunsInFlight; ++u) {
-      const uint32_t i = (s[D][u] & ~1u) + 2u * lane;
-      v[D][u] = i < e[D][u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
-    }
+    for (int u = 0; u < kDRunsInFlight; ++u)
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const uint32_t i = (s[D][u] & ~1u) + 2u * (lane + q * g);
+        v[D][u][q] = i < e[D][u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
+      }
     uint32_t sn[kDRunsInFlight], en[kDRunsInFlight];
     depth_run_bounds(row0, row1, c0 + (D + 1) * round, groups, n_chunks, sn, en);
-    // round i: count its records
+    // round i: count its records (a run longer than the prefetched P * 2g
+    // records continues with loads of its own)
 #pragma unroll
     for (int u = 0; u < kDRunsInFlight; ++u) {
       const uint32_t i = (s[0][u] & ~1u) + 2u * lane;
-      depth_pair(keys, counts, v[0][u], i, s[0][u], e[0][u]);
-      for (uint32_t j = i + 2u * g; j < e[0][u]; j += 2u * g)
+#pragma unroll
+      for (int q = 0; q < P; ++q)
+        depth_pair(keys, counts, v[0][u][q], i + 2u * q * g, s[0][u], e[0][u]);
+      for (uint32_t j = i + 2u * P * g; j < e[0][u]; j += 2u * g)
         depth_pair(keys, counts, *reinterpret_cast<const uint4 *>(rec + j), j, s[0][u], e[0][u]);
     }
 #pragma unroll
     for (int r = 0; r < D; ++r)
 #pragma unroll
       for (int u = 0; u < kDRunsInFlight; ++u) {
-        v[r][u] = v[r + 1][u];
+#pragma unroll
+        for (int q = 0; q < P; ++q) v[r][u][q] = v[r + 1][u][q];
         s[r][u] = s[r + 1][u];
         e[r][u] = e[r + 1][u];
       }
@@ -481,17 +490,21 @@ __device__ inline void tile_accumulate(const uint16_t *__restrict__ rec,
       s[u] += base;
       e[u] += base;
     }
-    uint4 v[kRunsInFlight];
+    constexpr int P = kPasses;
+    uint4 v[kRunsInFlight][P];
+#pragma unroll
+    for (int u = 0; u < kRunsInFlight; ++u)
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const uint32_t i = (s[u] & ~7u) + 8u * (lane + q * g);
+        v[u][q] = i < e[u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
+      }
 #pragma unroll
     for (int u = 0; u < kRunsInFlight; ++u) {
       const uint32_t i = (s[u] & ~7u) + 8u * lane;
-      v[u] = i < e[u] ? *reinterpret_cast<const uint4 *>(rec + i) : make_uint4(0u, 0u, 0u, 0u);
-    }
 #pragma unroll
-    for (int u = 0; u < kRunsInFlight; ++u) {
-      const uint32_t i = (s[u] & ~7u) + 8u * lane;
-      count_records(tile, v[u], i, s[u], e[u]);
-      for (uint32_t j = i + 8u * g; j < e[u]; j += 8u * g)
+      for (int q = 0; q < P; ++q) count_records(tile, v[u][q], i + 8u * q * g, s[u], e[u]);
+      for (uint32_t j = i + 8u * P * g; j < e[u]; j += 8u * g)
         count_records(tile, *reinterpret_cast<const uint4 *>(rec + j), j, s[u], e[u]);
     }
   }

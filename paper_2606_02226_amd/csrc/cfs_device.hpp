@@ -341,8 +341,8 @@ __device__ __forceinline__ double sqrt_r(double a) { return sqrt_f64(a); }
 __device__ __forceinline__ float cos_r(float a) { return cosf(a); }
 __device__ __forceinline__ double cos_r(double a) { return cos(a); }
 
-template <typename real, int FINAL, int DIM>
-__device__ __forceinline__ void final_transform(const float *__restrict__ fp, const real p[DIM],
+template <typename real, int FINAL, int DIM, typename P = float>
+__device__ __forceinline__ void final_transform(const P *__restrict__ fp, const real p[DIM],
                                                 real q[2], real *depth) {
   if constexpr (FINAL == kFinalSwirl) {
     const real cx = fp[0], cy = fp[1], kappa = fp[2], tx = fp[3], ty = fp[4];

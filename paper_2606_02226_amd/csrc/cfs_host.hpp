@@ -8,8 +8,9 @@
 
 namespace cfs {
 
+constexpr int kFinalParams = 24;
 struct FinalArgs {
-  float p[24];
+  float p[kFinalParams];
 };
 
 struct ChaosJob {

@@ -100,11 +100,16 @@ constexpr int kDTileBits = 13;
 constexpr uint32_t kDTileElems = 1u << kDTileBits;
 constexpr int kDAccBlock = 1024;  // one per CU (96 KB of LDS): 4 waves per SIMD
 
-// Lanes per run of the depth accumulate, 2^log2g: the smallest group whose
-// one pass of two records per lane covers a run of the mean length plus one
-// (the even record below the start).
+// The depth accumulate's lanes prefetch kDPasses 16-byte loads (two records
+// each) per run.  Lanes per run, 2^log2g: the smallest group whose
+// prefetch covers a run of the mean length plus one (the even record below
+// the start).  The accumulate waits on its scattered loads, and the runs it
+// has in flight set its rate: few lanes per run, each with several loads,
+// keep the most runs in flight (4 loads of 2 lanes per 15-record run: 3.98
+// ms per Menger step; 1 load of 8 lanes: 6.63; 2 loads of 4 lanes: 4.63).
+constexpr int kDPasses = 4;
 __host__ __device__ inline uint32_t depth_run_lanes_log2(uint64_t mean_run) {
-  const uint64_t need = mean_run + 1u;
+  const uint64_t need = (mean_run + 1u + kDPasses - 1u) / kDPasses;
   uint32_t lg = 0;
   while (lg < 5 && (2ull << lg) < need) ++lg;
   return lg;
@@ -117,11 +122,15 @@ constexpr uint32_t kAccTargetGroups = 512;
 // still fill the chip when much of the image is empty.
 constexpr uint32_t kAccTargetSkip = 4 * kAccTargetGroups;
 
-// Lanes per run of the count accumulate, 2^log2g: the smallest group whose
-// one pass of 8 records per lane covers a run of the mean length plus three
-// (longer runs take further passes; larger groups measured slower).
+// The count accumulate's lanes prefetch kPasses 16-byte loads (8 records
+// each) per run.  Lanes per run, 2^log2g: the smallest group whose prefetch
+// covers a run of the mean length plus three (longer runs take further
+// loads; larger groups measured slower, and so did 2 or 4 loads per lane
+// with smaller groups: 0.44 and 0.52 against 0.42 ms on the CFS square,
+// whose two-workgroup-per-CU accumulate already holds many runs in flight).
+constexpr int kPasses = 1;
 __host__ __device__ inline uint32_t run_lanes_log2(uint64_t mean_run) {
-  const uint64_t need = mean_run + 3u;
+  const uint64_t need = (mean_run + 3u + kPasses - 1u) / kPasses;
   uint32_t lg = 0;
   while (lg < 5 && (8ull << lg) < need) ++lg;
   return lg;

@@ -50,11 +50,13 @@ __global__ __launch_bounds__(kDBlock) void k_chaos_depth_binned(MapTable<3> mt, 
   __shared__ uint2 stage[kDCap];
   __shared__ uint32_t cnt[kMaxTiles];
   __shared__ uint32_t wsum[kDWaves + 1];
+  __shared__ real fparams[kFinalParams];
   load_table<real, 3, sizeof(real) == sizeof(double), LIN != kLinGeneral>(mt, table, th);
   for (uint32_t t = threadIdx.x; t < ba.n_tiles; t += kDBlock) cnt[t] = 0u;
+  if (threadIdx.x < kFinalParams) fparams[threadIdx.x] = static_cast<real>(fa.p[threadIdx.x]);
   __syncthreads();
   chaos_depth_block<real, EQUAL ? kSelEqual : kSelTable, LIN>(
-      table, th, mt.n_maps, mt.n_search, win, ra, fa.p, near_plane, ba, out, blockIdx.x, stage,
+      table, th, mt.n_maps, mt.n_search, win, ra, fparams, near_plane, ba, out, blockIdx.x, stage,
       cnt, wsum, shared_linear<real, 3>(mt));
 }
 

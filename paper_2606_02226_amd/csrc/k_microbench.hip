@@ -14,7 +14,11 @@
 //              Gaussian accumulate's fixed-point tap sums);
 //   lds_min    uniformly random u64 atomic minima into 64 KiB of LDS (the
 //              depth accumulate's key tile);
-//   philox     Philox4x32-10 blocks (the chaos game's random numbers).
+//   philox     Philox4x32-10 blocks (the chaos game's random numbers);
+//   runs       reads of runs of 128, 512 or 2048 bytes at uniformly random
+//              16-byte-aligned places in a large buffer, a group of lanes
+//              per run and 16 bytes per lane, four runs in flight per group
+//              (the accumulates read each chunk's run of their tile so).
 // Addresses come from a per-lane linear congruential sequence (one 32-bit
 // multiply-add per operation) scaled to the working set by a high multiply,
 // so the address arithmetic is small next to the operation it feeds.  The
@@ -120,6 +124,31 @@ __global__ __launch_bounds__(kMbBlock) void k_mb_philox(uint32_t *__restrict__ o
   out[g] = acc;
 }
 
+// Groups of 2^LOG2G lanes; each group reads `per_group` runs of 2^LOG2G
+// 16-byte vectors starting at random vectors of [0, n_start), four at a
+// time; one word per lane is written so the loads are kept.
+template <int LOG2G>
+__global__ __launch_bounds__(kMbBlock) void k_mb_runs(const uint4 *__restrict__ buf,
+                                                      uint32_t n_start, uint32_t per_group,
+                                                      uint32_t *__restrict__ out) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lane = g & ((1u << LOG2G) - 1u);
+  // the same sequence in every lane of a group
+  uint32_t h = (g >> LOG2G) * 0x9E3779B9u + 0x7F4A7C15u;
+  uint32_t acc = 0;
+  for (uint32_t i = 0; i < per_group; i += 4) {
+    uint4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      h = h * kLcgMul + kLcgAdd;
+      v[u] = buf[static_cast<size_t>(__umulhi(h, n_start)) + lane];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  out[g] = acc;
+}
+
 uint32_t per_lane_of(uint64_t ops, uint64_t lanes) {
   const uint64_t p = (ops + lanes - 1) / lanes;
   return static_cast<uint32_t>(p < 1 ? 1 : (p > 0xFFFFFFFFull ? 0xFFFFFFFFull : p));
@@ -189,6 +218,35 @@ extern "C" int cfs_microbench(int32_t kind, void *buf, size_t bytes, uint64_t op
       hipLaunchKernelGGL(k_mb_philox, dim3(kMbGrid), dim3(kMbBlock), 0, s,
                          static_cast<uint32_t *>(buf), pl);
       *done = lanes * pl;
+      break;
+    }
+    case CFS_MB_RUNS_128:
+    case CFS_MB_RUNS_512:
+    case CFS_MB_RUNS_2048: {
+      // buf = [lanes words written | the runs' buffer]
+      const int lg = kind == CFS_MB_RUNS_128 ? 3 : (kind == CFS_MB_RUNS_512 ? 5 : 7);
+      const uint32_t vec = 1u << lg;  // 16-byte vectors per run
+      const size_t head = (lanes * 4 + 255) & ~static_cast<size_t>(255);
+      if (bytes < head + (static_cast<size_t>(vec) << 4) * 2)
+        return fail(CFS_E_INVALID, "buf must hold one word per lane and two runs");
+      const uint64_t nv = (bytes - head) / 16;
+      const uint64_t n_start = nv - vec + 1;
+      if (n_start > 0xFFFFFFFFull) return fail(CFS_E_INVALID, "runs buffer above 64 GiB");
+      const uint64_t groups = lanes >> lg;
+      uint32_t pg = per_lane_of(ops, groups);
+      pg = (pg + 3u) & ~3u;
+      const uint4 *runs = reinterpret_cast<const uint4 *>(static_cast<char *>(buf) + head);
+      uint32_t *words = static_cast<uint32_t *>(buf);
+      if (lg == 3)
+        hipLaunchKernelGGL(k_mb_runs<3>, dim3(kMbGrid), dim3(kMbBlock), 0, s, runs,
+                           static_cast<uint32_t>(n_start), pg, words);
+      else if (lg == 5)
+        hipLaunchKernelGGL(k_mb_runs<5>, dim3(kMbGrid), dim3(kMbBlock), 0, s, runs,
+                           static_cast<uint32_t>(n_start), pg, words);
+      else
+        hipLaunchKernelGGL(k_mb_runs<7>, dim3(kMbGrid), dim3(kMbBlock), 0, s, runs,
+                           static_cast<uint32_t>(n_start), pg, words);
+      *done = groups * pg * (static_cast<uint64_t>(vec) << 4);  // bytes read
       break;
     }
     default:

@@ -446,10 +446,15 @@ def test_microbench_validation(L):
     # placeholder addresses are never dereferenced: each call fails first
     assert lib.cfs_microbench(0, C.c_void_p(255), 64, 0, C.byref(done), None) == L.CFS_E_INVALID
     assert "aligned" in lib.cfs_last_error().decode()
-    assert lib.cfs_microbench(9, C.c_void_p(256), 64, 0, C.byref(done), None) == L.CFS_E_INVALID
+    assert lib.cfs_microbench(10, C.c_void_p(256), 64, 0, C.byref(done), None) == L.CFS_E_INVALID
     assert "unknown microbenchmark" in lib.cfs_last_error().decode()
     assert lib.cfs_microbench(0, C.c_void_p(256), 16, 0, C.byref(done), None) == L.CFS_E_INVALID
     assert lib.cfs_microbench(1, C.c_void_p(256), 2, 1, C.byref(done), None) == L.CFS_E_INVALID
     assert lib.cfs_microbench(3, C.c_void_p(256), 1024, 1, C.byref(done), None) == L.CFS_E_INVALID
     assert lib.cfs_microbench(5, C.c_void_p(256), 1024, 1, C.byref(done), None) == L.CFS_E_INVALID
+    # run reads: 4 MiB of lane words plus at least two runs
+    for kind in (7, 8, 9):
+        assert lib.cfs_microbench(kind, C.c_void_p(256), 4 << 20, 1, C.byref(done),
+                                  None) == L.CFS_E_INVALID
+        assert "two runs" in lib.cfs_last_error().decode()
     assert done.value == 7

@@ -1,6 +1,7 @@
 """The ceiling probes (cfs_microbench) do the work they report: the copy
 copies, every random atomic add lands once, atomic minima only lower
-values, and the Philox probe's blocks are the generator's."""
+values, the Philox probe's blocks are the generator's, and the run reads read
+what their address sequence names."""
 import numpy as np
 import pytest
 
@@ -68,3 +69,34 @@ def test_philox_blocks(api, orc):
             b = orc.philox_many(seed, np.array([[g, i, 0, 0]], np.uint32))[0]
             ref ^= int(b[0] ^ b[1] ^ b[2] ^ b[3])
         assert int(got[g]) == ref, g
+
+
+@pytest.mark.parametrize("kind,lg", [("runs_128", 3), ("runs_512", 5), ("runs_2048", 7)])
+def test_run_reads(api, kind, lg):
+    """Each lane's word is the xor of the 16-byte vectors it read: run
+    starts from its group's congruential sequence, scaled to the buffer by a
+    high multiply, and the lane's vector within the run."""
+    lanes, head = 4096 * 256, 4 << 20
+    nbytes = head + (16 << 20)
+    buf = torch.zeros(nbytes, dtype=torch.uint8, device=_dev())
+    nw = (nbytes - head) // 4
+    words = (np.arange(nw, dtype=np.uint64) * 2654435761 % (1 << 32)).astype(np.uint32)
+    buf[head:] = torch.from_numpy(words.view(np.uint8)).to(_dev())
+    ops = 1 << 18
+    done = api.microbench(kind, buf, ops=ops)
+    torch.cuda.synchronize()
+    groups = lanes >> lg
+    pg = -(-ops // groups)
+    pg = (pg + 3) // 4 * 4
+    assert done == groups * pg * (16 << lg)
+    got = buf[:lanes * 4].view(torch.int32).cpu().numpy().view(np.uint32)
+    vec = words.reshape(-1, 4)
+    n_start = vec.shape[0] - (1 << lg) + 1
+    for g in (0, 1, (1 << lg) + 3, lanes - 1):
+        h = ((g >> lg) * 0x9E3779B9 + 0x7F4A7C15) % (1 << 32)
+        acc = 0
+        for _ in range(pg):
+            h = (h * 1664525 + 1013904223) % (1 << 32)
+            v = vec[((h * n_start) >> 32) + (g & ((1 << lg) - 1))]
+            acc ^= int(v[0] ^ v[1] ^ v[2] ^ v[3])
+        assert int(got[g]) == acc, g
