@@ -276,7 +276,16 @@ __device__ __forceinline__ void load_table(const MapTable<DIM> &mt, real *table,
 constexpr int kSinCosTable = 256;
 __shared__ double2 s_sincos[kSinCosTable];
 
-__device__ __noinline__ void sincos_f64_wide(double a, double *sn, double *cs) { sincos(a, sn, cs); }
+// Out of line (the rare wide-angle case), returning in registers: results
+// passed back through memory would leave loads in flight at the join with
+// the inline path, and the wait for them (the memory counter is in order)
+// would also wait for every store the kernel has in flight, such as the
+// binned splat's record writes.
+__device__ __noinline__ double2 sincos_f64_wide(double a) {
+  double sn, cs;
+  sincos(a, &sn, &cs);
+  return make_double2(sn, cs);
+}
 
 __device__ inline void load_sincos_table() {
   for (int i = threadIdx.x; i < kSinCosTable; i += blockDim.x) {
@@ -290,7 +299,9 @@ __device__ inline void load_sincos_table() {
 
 __device__ __forceinline__ void sincos_f64(double a, double *sn, double *cs) {
   if (!(fabs(a) < 25000.0)) {
-    sincos_f64_wide(a, sn, cs);
+    const double2 w = sincos_f64_wide(a);
+    *sn = w.x;
+    *cs = w.y;
     return;
   }
   const double k = rint(a * 40.743665431525205956834243423364);
