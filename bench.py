@@ -127,7 +127,7 @@ def _workload(name):
     return {"menger": workloads.menger, "cfs_square": workloads.cfs_square,
             "sierpinski": workloads.sierpinski,
             # the paper's circle primitive alone, and mixed with two affine
-            # maps (the kernels then sort points by the kind of map drawn)
+            # maps (one system whose waves draw both kinds of map)
             "circle": lambda: workloads.circle(n_points=1 << 22),
             "circle_mixed": lambda: workloads.circle(n_points=1 << 22, extra_affine=2)}[name]()
 
@@ -146,7 +146,7 @@ STEP_KERNELS = {
 }
 
 
-def summarise_valu(directory, workload, precision):
+def summarise_valu(directory, workload, precision, out_dir=None):
     """Write profiles/valu_<workload>_<precision>.json from a rocprofv3 --pmc
     run of this benchmark with SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU and SQ_WAVES:
     mean per chaos-kernel dispatch, and the VALU wave-instructions issued per
@@ -169,7 +169,7 @@ def summarise_valu(directory, workload, precision):
     out["command"] = ("rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVES --output-format csv "
                       f"-d DIR -- python3 bench.py --workload {workload} --steps 2 --warmup 1 "
                       f"--no-cpu-baseline --no-forms --no-configs --no-ceilings --precision {precision}")
-    path = os.path.join(ROOT, "profiles", f"valu_{workload}_{precision}.json")
+    path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"valu_{workload}_{precision}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
@@ -184,7 +184,7 @@ def _csv_rows(directory, suffix):
         return list(csv.DictReader(fh))
 
 
-def summarise_trace(directory, log_path, workload, precision, steps=5, warmup=2):
+def summarise_trace(directory, log_path, workload, precision, steps=5, warmup=2, out_dir=None):
     """Write profiles/trace_<workload>_<precision>.md from a rocprofv3
     --kernel-trace --stats run of this benchmark (--steps 5 --warmup 2) and
     the JSON line that run printed (log_path): the kernel statistics, the
@@ -240,13 +240,13 @@ def summarise_trace(directory, log_path, workload, precision, steps=5, warmup=2)
             f"{roof['peak']:.2f} T = **{frac:.3f}** (the line: {roof['frac']:.3f}).", ""]
     out += ["Phases of the bench line (ms per step): " +
             ", ".join(f"{k} {v:.3f}" for k, v in line["phase_ms"].items()) + ".", ""]
-    path = os.path.join(ROOT, "profiles", f"trace_{workload}_{precision}.md")
+    path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"trace_{workload}_{precision}.md")
     with open(path, "w") as fh:
         fh.write("\n".join(out))
     print("\n".join(out))
 
 
-def summarise_pmc(fetch_dir, write_dir, workload, precision):
+def summarise_pmc(fetch_dir, write_dir, workload, precision, out_dir=None):
     """Write profiles/traffic_<workload>_<precision>.json from two rocprofv3
     --pmc runs of this benchmark with --calibration-copy (FETCH_SIZE, then
     WRITE_SIZE; both in KiB per dispatch).  Each counter is scaled by the
@@ -269,7 +269,7 @@ def summarise_pmc(fetch_dir, write_dir, workload, precision):
                       f"-- python3 bench.py --workload {workload} --steps 2 --warmup 1 "
                       "--no-cpu-baseline --no-forms --no-configs --no-ceilings "
                       f"--calibration-copy --precision {precision}")
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_{workload}_{precision}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))

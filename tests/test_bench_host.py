@@ -46,3 +46,107 @@ def test_all_cores_depth_figure_is_the_oracle_image():
     assert np.array_equal(img["density"], ref["density"])
     err = bench.parity_error(dict(ref), img)
     assert err["keys_differing"] == 0 and err["density_rel_l1"] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# The profile summarisers, on synthetic rocprofv3 outputs with known figures
+# ---------------------------------------------------------------------------
+def _write_csv(path, header, rows):
+    import csv
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def _counter_rows(counter, items):
+    return [[i + 1, i + 1, "Agent 1", 1, 1, 1, 64, 1, name, 256, 0, 0, 8, 0, 16, counter,
+             float(v), 0, 1] for i, (name, v) in enumerate(items)]
+
+
+_COUNTER_HEADER = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id",
+                   "Thread_Id", "Grid_Size", "Kernel_Id", "Kernel_Name", "Workgroup_Size",
+                   "LDS_Block_Size", "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count",
+                   "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp",
+                   "End_Timestamp"]
+
+
+def test_summarise_pmc_scales_by_the_copy(tmp_path):
+    """Bytes per step = sum over the three profiled steps' dispatches / 3,
+    in KiB, times the factor that makes the 256 MiB copy read 256 MiB."""
+    import bench
+    chaos = "void cfs::k_chaos_depth_binned<double, true, 2>(args)"
+    acc = "cfs::k_depth_accumulate(args)"
+    copy = "__amd_rocclr_copyBuffer"
+    # the counter reads half the copy: the factor is 2
+    fetch = [(copy, 131072.0)] + [(chaos, 10.0)] * 12 + [(acc, 3000.0)] * 12
+    write = [(copy, 262144.0)] + [(chaos, 2000.0)] * 12 + [(acc, 50.0)] * 12
+    _write_csv(str(tmp_path / "f" / "vm" / "1_counter_collection.csv"), _COUNTER_HEADER,
+               _counter_rows("FETCH_SIZE", fetch))
+    _write_csv(str(tmp_path / "w" / "vm" / "1_counter_collection.csv"), _COUNTER_HEADER,
+               _counter_rows("WRITE_SIZE", write))
+    bench.summarise_pmc(str(tmp_path / "f"), str(tmp_path / "w"), "menger", "f64",
+                        out_dir=str(tmp_path))
+    out = json.load(open(tmp_path / "traffic_menger_f64.json"))
+    assert out["calibration"]["FETCH_SIZE"]["scale"] == 2.0
+    assert out["calibration"]["WRITE_SIZE"]["scale"] == 1.0
+    k = out["kernels"]
+    assert k["chaos_kernel"]["FETCH_SIZE"] == 12 * 10.0 / 3 * 1024 * 2
+    assert k["tile_accumulate"]["FETCH_SIZE"] == 12 * 3000.0 / 3 * 1024 * 2
+    assert k["chaos_kernel"]["WRITE_SIZE"] == 12 * 2000.0 / 3 * 1024
+    assert out["source_digest"] == bench.source_digest()
+
+
+def test_summarise_valu_per_point_iteration(tmp_path):
+    """VALU wave-instructions per point-iteration from the per-dispatch
+    counters, with the launches per step read off SQ_WAVES."""
+    import bench
+    import workloads as W
+    w = W.menger()
+    N, T = w["run"]["n_points"], w["run"]["n_iters"]
+    chaos = "void cfs::k_chaos_depth_binned<double, true, 2>(args)"
+    waves = N / 64 / 4            # four launches per step
+    insts = 90.0 * N * T / 64 / 4  # 90 per point-iteration
+    rows = []
+    for c, v in (("SQ_INSTS_VALU", insts), ("SQ_ACTIVE_INST_VALU", insts), ("SQ_WAVES", waves)):
+        rows += _counter_rows(c, [(chaos, v)] * 12)
+    _write_csv(str(tmp_path / "v" / "vm" / "1_counter_collection.csv"), _COUNTER_HEADER, rows)
+    bench.summarise_valu(str(tmp_path / "v"), "menger", "f64", out_dir=str(tmp_path))
+    out = json.load(open(tmp_path / "valu_menger_f64.json"))
+    assert out["launches_per_step"] == 4
+    assert abs(out["valu_insts_per_point_iteration"] - 90.0) < 1e-9
+
+
+def test_summarise_trace_fraction(tmp_path):
+    """The roofline kernel's mean over the timed steps' launches, and the
+    fraction of the VALU model that mean gives."""
+    import bench
+    chaos = "void cfs::k_chaos_depth_binned<double, true, 2>(args)"
+    steps, warmup, per = 5, 2, 4
+    trace_header = ["Kind", "Agent_Id", "Queue_Id", "Stream_Id", "Thread_Id", "Dispatch_Id",
+                    "Kernel_Id", "Kernel_Name", "Correlation_Id", "Start_Timestamp",
+                    "End_Timestamp", "LDS_Block_Size", "Scratch_Size", "VGPR_Count",
+                    "Accum_VGPR_Count", "SGPR_Count", "Workgroup_Size_X", "Workgroup_Size_Y",
+                    "Workgroup_Size_Z", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"]
+    rows, t = [], 0
+    for i in range((steps + warmup) * per):
+        dur = 3_000_000 if i < warmup * per else 1_500_000  # ns: warm-up launches slower
+        rows.append(["KERNEL_DISPATCH", "Agent 1", 1, 0, 1, i + 1, 7, chaos, i + 1, t, t + dur,
+                     145408, 0, 128, 0, 112, 1024, 1, 1, 1 << 24, 1, 1])
+        t += dur + 1000
+    _write_csv(str(tmp_path / "t" / "m_kernel_trace.csv"), trace_header, rows)
+    _write_csv(str(tmp_path / "t" / "m_kernel_stats.csv"),
+               ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs",
+                "StdDev"],
+               [[chaos, len(rows), 1.0, 1.0, 100.0, 1.0, 1.0, 0.0]])
+    line = {"metric": "m", "ms_per_step": 7.0, "config": {"workload": "menger: test"},
+            "phase_ms": {"chaos_kernel": 6.0, "table_transpose": 0.3, "tile_accumulate": 0.7},
+            "roofline": {"lane_ops_per_step": 1.2e11, "peak": 40.0, "frac": 0.5}}
+    log = tmp_path / "run.log"
+    log.write_text("profiler noise\n" + json.dumps(line) + "\nmore noise\n")
+    bench.summarise_trace(str(tmp_path / "t"), str(log), "menger", "f64", out_dir=str(tmp_path))
+    text = (tmp_path / "trace_menger_f64.md").read_text()
+    # 4 timed launches of 1.5 ms per step: 6.0 ms; 1.2e11 / 6 ms / 40 T = 0.5
+    assert "6.000 ms per step in the trace" in text
+    assert "**0.500**" in text
