@@ -106,8 +106,8 @@ enum { CFS_PREC_F32 = 0, CFS_PREC_F64 = 1 };
  * every tile in LDS and merges it into the image (needs workspace; count
  * images of at most 2^25 elements, depth images of at most 2^24 pixels).
  * One workgroup's records must fit one launch's record budget (2^29 16-bit
- * count records or 2^28 8-byte depth records), which holds about 10^6
- * splatted steps per point (count images) or 2.6 x 10^5 (depth images);
+ * count records or 2^30 8-byte depth records), which holds about 10^6
+ * splatted steps per point;
  * longer runs take DIRECT under AUTO and are refused
  * (CFS_E_UNSUPPORTED) under BINNED.  AUTO picks BINNED for large runs that
  * qualify.  Both give bit-identical images (integer sums and minima do not

@@ -278,12 +278,13 @@ extern "C" int cfs_image_clear(const cfs_image *img, void *stream) {
 namespace {
 
 // Records of one launch of the binned path: 2^29 16-bit count records
-// (1 GiB) or 2^28 8-byte depth records (2 GiB), which keeps record indices
+// (1 GiB) or 2^30 8-byte depth records (8 GiB), which keeps record indices
 // within 31 bits and chunk indices within 24 (the kernels index records in
 // 32-bit arithmetic).  Each launch ends with a read-modify-write of the
-// image's occupied tiles, so depth runs (192 MiB of image) take the larger
-// budget: the 3D workload of 2^26 points x 16 splats needs four launches.
-uint64_t binned_record_budget(bool depth) { return depth ? (1ull << 28) : (1ull << 29); }
+// image's occupied tiles and each accumulate workgroup's tail, so depth runs
+// (192 MiB of image) take the larger budget: the 3D workload of 2^26 points
+// x 16 splats is one launch (four launches of 2^28 records took 2.5% longer).
+uint64_t binned_record_budget(bool depth) { return depth ? (1ull << 30) : (1ull << 29); }
 
 uint64_t binned_block_records(const cfs_run *run, bool depth, uint32_t per_iter) {
   const uint64_t slots = depth ? kDSlots : kBinSlots;
@@ -294,20 +295,20 @@ uint64_t binned_block_records(const cfs_run *run, bool depth, uint32_t per_iter)
 }
 
 // Whether one workgroup's records fit the budget of a launch (runs of more
-// than about 10^6 splats per point for counts, 5 x 10^5 for depth, do not,
-// and take the direct splat).
+// than about 10^6 splats per point do not, and take the direct splat).
 bool binned_fits(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
   return binned_block_records(run, depth, per_iter) <= binned_record_budget(depth);
 }
 
-// Points per launch of the binned path: at most 2^24, and few enough that the
-// records of one launch stay within binned_record_budget() (the caller has
-// checked binned_fits(), so one workgroup's records always do).
+// Points per launch of the binned path: few enough that the records of one
+// launch stay within binned_record_budget() (the caller has checked
+// binned_fits(), so one workgroup's records always do), and for count images
+// at most 2^24.
 uint32_t binned_slice(const cfs_run *run, bool depth, uint32_t per_iter = 1) {
   uint64_t max_blocks = binned_record_budget(depth) / binned_block_records(run, depth, per_iter);
   if (max_blocks < 1) max_blocks = 1;
   uint64_t pts = max_blocks * (depth ? kDBlock : kBinBlock);
-  if (pts > (1ull << 24)) pts = 1ull << 24;
+  if (!depth && pts > (1ull << 24)) pts = 1ull << 24;
   if (pts > run->n_points) pts = run->n_points;
   return static_cast<uint32_t>(pts);
 }

@@ -423,19 +423,19 @@ def test_binned_record_budget(L):
     rc = lib.cfs_chaos_scene(C.byref(s), objs, 8, C.byref(scene), C.byref(img), None, 0, None)
     assert rc == L.CFS_E_UNSUPPORTED
     assert "record budget" in lib.cfs_last_error().decode()
-    # depth images: 2^28 records of 8 bytes, 16384 chunks of 16384 per
-    # workgroup, i.e. 262144 splatted steps per point
+    # depth images: 2^30 records of 8 bytes, 65536 chunks of 16384 per
+    # workgroup, i.e. 1048576 splatted steps per point: the longest run
+    # (n_iters = 2^20, no burn-in) fits one workgroup, with one workgroup per
+    # launch (8 GiB of records)
     s3, keep3 = _system(L, dim=3, n=3, final_kind=2)
     dimg = L.CfsImage(2, 64, 64, 1, (C.c_float * 2)(-1, -1), (C.c_float * 2)(1, 1), 0.1,
                       C.c_void_p(256), C.c_void_p(512), None)  # never dereferenced
-    dfits = L.CfsRun(0, 0, 1 << 12, 0, (1 << 18) + 8, 8, 0, 2)
-    assert lib.cfs_chaos_game_workspace(C.byref(s3), C.byref(dfits), C.byref(dimg)) > 0
-    dover = L.CfsRun(0, 0, 1 << 12, 0, (1 << 18) + 9, 8, 0, 2)
-    assert lib.cfs_chaos_game_workspace(C.byref(s3), C.byref(dover), C.byref(dimg)) == 0
-    rc = lib.cfs_chaos_game(C.byref(s3), C.byref(dover), C.byref(dimg), None, None, None, None,
+    dmax = L.CfsRun(0, 0, 1 << 12, 0, 1 << 20, 0, 0, 2)
+    ws = lib.cfs_chaos_game_workspace(C.byref(s3), C.byref(dmax), C.byref(dimg))
+    assert ws >= (1 << 30) * 8
+    rc = lib.cfs_chaos_game(C.byref(s3), C.byref(dmax), C.byref(dimg), None, None, None, None,
                             0, None)
-    assert rc == L.CFS_E_UNSUPPORTED
-    assert "record budget" in lib.cfs_last_error().decode()
+    assert rc == L.CFS_E_WORKSPACE  # nothing was passed; nothing is launched
 
 
 def test_microbench_validation(L):

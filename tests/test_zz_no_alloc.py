@@ -27,7 +27,7 @@ def _lib():
 def test_refuses_runs_beyond_the_scratch():
     """A depth run with 70000 splatted steps per point: one workgroup's 8-byte
     records alone (4375 chunks of 16384) take 573 MB, more than the 256 MiB
-    array, while they fit cfs_chaos_game's launch budget (2^28 records).  BINNED is
+    array, while they fit cfs_chaos_game's launch budget (2^30 records).  BINNED is
     refused before anything is enqueued; nothing is dereferenced."""
     L = _lib()
     lib = L.load()
@@ -41,7 +41,7 @@ def test_refuses_runs_beyond_the_scratch():
                      (C.c_float * 2)(1, 1), 0.1, C.c_void_p(256), C.c_void_p(512), None)
     steps = 70000
     binned = L.CfsRun(0, 0, 1 << 10, 0, steps + 4, 4, 1, L.SPLAT_PATHS["binned"], 0)
-    # cfs_chaos_game takes it (the launch budget holds 2^28 records)
+    # cfs_chaos_game takes it (the launch budget holds 2^30 records)
     assert lib.cfs_chaos_game_workspace(C.byref(s), C.byref(binned), C.byref(img)) > 0
     rc = lib.cfs_chaos_game_noalloc(C.byref(s), C.byref(binned), C.byref(img), None, None, None,
                                     None)
