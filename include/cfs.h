@@ -216,8 +216,13 @@ size_t cfs_chaos_game_workspace(const cfs_system *sys, const cfs_run *run,
  *     double (F64): each point's position after n_iters steps.
  *   last_index:   device, nullable; uint8 [n_points]: index of the last map.
  *   indices:      device, nullable; uint8 [n_points][n_iters]: every index.
- *   workspace:    device scratch of cfs_chaos_game_workspace() bytes (may be
- *     NULL when that is 0); contents need no initialisation.
+ *   workspace:    device scratch, 256-byte aligned; contents need no
+ *     initialisation.  cfs_chaos_game_workspace() bytes give the fewest
+ *     launches (may be NULL when that is 0); a smaller workspace cuts the
+ *     binned splat into more point-range launches that fit it (the same
+ *     result), down to one workgroup's records; below that CFS_SPLAT_AUTO
+ *     takes the direct splat and CFS_SPLAT_BINNED fails with
+ *     CFS_E_WORKSPACE.
  * Returns CFS_OK or a negative CFS_E_* code (nothing enqueued on error). */
 int cfs_chaos_game(const cfs_system *sys, const cfs_run *run,
                    const cfs_image *img, void *final_points,

@@ -141,8 +141,9 @@ def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
     """Enqueue the plain chaos game (cfs_chaos_game) into ``image``.
 
     ``splat_path`` is 'auto', 'direct' or 'binned'; ``workspace`` is an
-    optional uint8 device tensor reused across calls (allocated here when
-    missing or too small).
+    optional uint8 device tensor reused across calls (allocated here, of the
+    size for the fewest launches, when missing; a smaller one is used as it
+    is, and the library cuts the run into launches that fit it).
 
     ``system`` is a workload system dict or a :class:`System`; ``final``
     (float32/float64 [N][dim]), ``last`` (uint8 [N]) and ``indices``
@@ -156,15 +157,15 @@ def chaos_game(system, run, image, *, precision="f32", final=None, last=None,
     runc = run_struct(run, precision, splat_path)
     ws_bytes = lib.cfs_chaos_game_workspace(C.byref(sysc.struct), C.byref(runc),
                                             C.byref(image.struct))
-    ws = None
+    ws, nbytes = None, 0
     if ws_bytes:
-        if workspace is not None and workspace.numel() >= ws_bytes:
-            ws = workspace
+        if workspace is not None:
+            ws, nbytes = workspace, workspace.numel() * workspace.element_size()
         else:
-            ws = _scratch(ws_bytes, image.data.device, stream)
+            ws, nbytes = _scratch(ws_bytes, image.data.device, stream), ws_bytes
     rc = lib.cfs_chaos_game(C.byref(sysc.struct), C.byref(runc), C.byref(image.struct),
                             _ptr(final), _ptr(last), _ptr(indices), _ptr(ws),
-                            C.c_size_t(ws_bytes), _stream_handle(stream))
+                            C.c_size_t(nbytes), _stream_handle(stream))
     check(rc, "cfs_chaos_game")
     return image
 

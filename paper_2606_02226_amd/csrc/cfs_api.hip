@@ -618,6 +618,14 @@ extern "C" int cfs_chaos_game(const cfs_system *sys, const cfs_run *run_in, cons
   ChaosCall cc;
   int rc = chaos_prepare(sys, run_in, img, final_points, last_index, indices, 0, &cc);
   if (rc) return rc;
+  // a workspace smaller than the fewest launches need: launches that fit it
+  if (cc.job.binned && workspace && workspace_bytes < cc.need) {
+    rc = chaos_prepare(sys, run_in, img, final_points, last_index, indices, workspace_bytes, &cc);
+    if (rc == CFS_E_UNSUPPORTED && run_in->splat_path == CFS_SPLAT_BINNED)
+      return fail(CFS_E_WORKSPACE, "binned splat: one workgroup's records exceed the %zu-byte "
+                  "workspace", workspace_bytes);
+    if (rc) return rc;
+  }
   if (cc.job.binned) {
     if (!workspace || workspace_bytes < cc.need)
       return fail(CFS_E_WORKSPACE, "binned splat needs %zu bytes of workspace, got %zu", cc.need,

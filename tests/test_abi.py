@@ -358,6 +358,26 @@ def test_binned_image_size_limit(L):
     assert "at most 33554432 elements" in lib.cfs_last_error().decode()
 
 
+def test_workspace_below_one_workgroup_refused(L):
+    # a workspace smaller than the fewest launches need is cut into more
+    # launches; one below a single workgroup's records is refused for BINNED
+    # before anything is enqueued (the pointers are never dereferenced)
+    lib = L.load()
+    s, keep = _system(L)
+    r = L.CfsRun(0, 0, 1 << 20, 0, 8, 2, 0, 2)
+    img = _image(L, W=256, H=256)
+    img.data = C.c_void_p(256)
+    need = lib.cfs_chaos_game_workspace(C.byref(s), C.byref(r), C.byref(img))
+    assert need > 4096
+    rc = lib.cfs_chaos_game(C.byref(s), C.byref(r), C.byref(img), None, None, None,
+                            C.c_void_p(4096), 4096, None)
+    assert rc == L.CFS_E_WORKSPACE
+    assert "one workgroup" in lib.cfs_last_error().decode()
+    rc = lib.cfs_chaos_game(C.byref(s), C.byref(r), C.byref(img), None, None, None, None, 0,
+                            None)
+    assert rc == L.CFS_E_WORKSPACE
+
+
 def test_continued_run_rules(L):
     # a continued run needs final_points (its start) and is for cfs_chaos_game
     # only; burn_in beyond n_iters is refused where runs cannot be continued

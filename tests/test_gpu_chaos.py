@@ -458,6 +458,9 @@ def test_binned_unequal_probabilities_3d(api, orc):
 
 
 def test_binned_workspace_too_small(api):
+    """Half the workspace of the fewest launches is enough (more launches);
+    one below a single workgroup's records is refused under BINNED, with
+    nothing written."""
     from paper_2606_02226_amd import _lib
     import ctypes as C
     w = W.cfs_square(n_points=1 << 16)
@@ -466,10 +469,18 @@ def test_binned_workspace_too_small(api):
     runc = api.run_struct(w["run"], "f64", "binned")
     need = _lib.load().cfs_chaos_game_workspace(C.byref(sysc.struct), C.byref(runc),
                                                 C.byref(img.struct))
-    small = torch.empty(int(need) // 2, dtype=torch.uint8, device=_dev())
+    half = torch.empty(int(need) // 2, dtype=torch.uint8, device=_dev())
     rc = _lib.load().cfs_chaos_game(C.byref(sysc.struct), C.byref(runc), C.byref(img.struct),
-                                    None, None, None, C.c_void_p(small.data_ptr()),
-                                    C.c_size_t(small.numel()), None)
+                                    None, None, None, C.c_void_p(half.data_ptr()),
+                                    C.c_size_t(half.numel()), None)
+    assert rc == _lib.CFS_OK
+    torch.cuda.synchronize()
+    assert np.array_equal(img.to_numpy()["image"], _image_of(api, w, "f64", "binned")["image"])
+    img.clear()
+    tiny = torch.empty(4096, dtype=torch.uint8, device=_dev())
+    rc = _lib.load().cfs_chaos_game(C.byref(sysc.struct), C.byref(runc), C.byref(img.struct),
+                                    None, None, None, C.c_void_p(tiny.data_ptr()),
+                                    C.c_size_t(tiny.numel()), None)
     assert rc == _lib.CFS_E_WORKSPACE
     assert int(img.to_numpy()["image"].astype(np.int64).sum()) == 0
 
@@ -544,6 +555,32 @@ def test_depth_ragged_tiles_vs_oracle(api, orc, shape):
     assert np.array_equal(got["density"], ref["density"])
     occupied, differ, occ_diff, ulps = depth_key_diff(got["depth"], ref["depth"])
     assert occ_diff == 0 and differ == 0, (differ, ulps)
+
+
+def test_small_workspace_takes_more_launches(api):
+    """A workspace below what the fewest launches need: the binned splat
+    runs in more point-range launches that fit it, with the same image; a
+    workspace below one workgroup's records takes the direct splat under
+    AUTO (the same image again)."""
+    w = W.menger(n_points=(1 << 17) + 5, side=512)
+    sysc = api.System(w["system"])
+    full = _depth_image(api, w, "f64", "binned")
+    need = api.chaos_workspace_bytes(sysc, w["run"], api.Image(w["image"], device=_dev()), "f64",
+                                     "binned")
+    for frac, path in ((3, "binned"), (7, "auto")):
+        ws = torch.empty(need // frac, dtype=torch.uint8, device=_dev())
+        img = api.Image(w["image"], device=_dev()).clear()
+        api.chaos_game(sysc, w["run"], img, precision="f64", splat_path=path, workspace=ws)
+        got = img.to_numpy()
+        assert np.array_equal(got["depth"], full["depth"])
+        assert np.array_equal(got["density"], full["density"])
+        assert got["dropped"] == full["dropped"]
+    tiny = torch.empty(1 << 16, dtype=torch.uint8, device=_dev())
+    img = api.Image(w["image"], device=_dev()).clear()
+    api.chaos_game(sysc, w["run"], img, precision="f64", splat_path="auto", workspace=tiny)
+    got = img.to_numpy()
+    assert np.array_equal(got["depth"], full["depth"])
+    assert np.array_equal(got["density"], full["density"])
 
 
 def test_depth_binned_vs_oracle(api, orc):
