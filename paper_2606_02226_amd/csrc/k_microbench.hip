@@ -234,7 +234,7 @@ extern "C" int cfs_microbench(int32_t kind, void *buf, size_t bytes, uint64_t op
       if (n_start > 0xFFFFFFFFull) return fail(CFS_E_INVALID, "runs buffer above 64 GiB");
       const uint64_t groups = lanes >> lg;
       uint32_t pg = per_lane_of(ops, groups);
-      pg = (pg + 3u) & ~3u;
+      pg = pg > 0xFFFFFFF0u ? 0xFFFFFFF0u : (pg + 3u) & ~3u;  // whole rounds of four
       const uint4 *runs = reinterpret_cast<const uint4 *>(static_cast<char *>(buf) + head);
       uint32_t *words = static_cast<uint32_t *>(buf);
       if (lg == 3)
