@@ -663,7 +663,7 @@ def forms(dev, precision, ceil):
                 + N * T * (per_point_iteration(2) + ADJOINT_STEP))                # sweep
     fwd_bound = {"valu_ms": fwd_valu / VALU_LANE_OPS_PEAK * 1e3}
     if ceil:
-        fwd_bound["lds_atomic_ms"] = taps / (ceil["lds_add_u64"]["G_per_s"] * 1e9) * 1e3
+        fwd_bound["lds_atomic_ms"] = taps / (ceil["lds_add_u32"]["G_per_s"] * 1e9) * 1e3
     bwd_bound = {"valu_ms": bwd_valu / VALU_LANE_OPS_PEAK * 1e3}
     out["grad"] = {
         "workload": "4-map affine system, 2^20 points x 32 iterations (8 burn-in), "
@@ -674,7 +674,7 @@ def forms(dev, precision, ceil):
         "full_trajectory_bytes": int(N * (T + 1) * 2 * 4),
         "roofline": {
             "forward": dict(fwd_bound, frac=max(fwd_bound.values()) / fwd_ms,
-                            what="64-bit LDS tap atomics (36 per splat, measured ceiling) "
+                            what="32-bit LDS tap atomics (36 per splat, measured ceiling) "
                                  "or VALU model, whichever is longer"),
             "backward": dict(bwd_bound, frac=max(bwd_bound.values()) / bwd_ms,
                              what="VALU model: records again, tap gradients, the sweep")},

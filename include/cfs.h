@@ -324,10 +324,12 @@ int cfs_chaos_scene(const cfs_system *sys, const cfs_object *objects, int32_t n_
  * (s = sigma_px; d = pixel centre - point, in pixels; pixel (i, j) gets
  * g(i + 0.5 - x) g(j + 0.5 - y); taps off the image are skipped) into the
  * FP32 density img (kind CFS_IMAGE_F32_DENSITY, one channel), which
- * ACCUMULATES sum(w) / (N (T - B)).  Each tap weight is rounded to a
- * multiple of 2^-31 and summed exactly per image tile; the tiles' sums are
- * added in FP32 in no fixed order, so results agree with any other order up
- * to rounding.
+ * ACCUMULATES sum(w) / (N (T - B)).  The records of an image tile are summed
+ * by several workgroups, each over its share of C records: each tap weight is
+ * rounded to a multiple of 2^-s with s = 32 - bit length of C (2^-21 for the
+ * usual shares of up to 2047 records; C taps then fit 32 bits) and summed
+ * exactly; the workgroups' sums are added in FP32 in no fixed order, so
+ * results agree with any other order up to rounding.
  *   ckpt: device, nullable; float [ceil(n_iters / ckpt_every)][n_points][2]:
  *     positions at iterations 0, c, 2c, ... (c = ckpt_every in 1..16), from
  *     which cfs_splat_backward recomputes its segments (written also when

@@ -169,6 +169,7 @@ constexpr uint32_t kGMaxParts = 64;
 constexpr uint32_t kGPartTarget = 32768;
 constexpr int kGBwdBlock = 256;
 constexpr int kMaxSeg = 16;  // longest checkpoint segment
+constexpr int kShortSeg = 8;  // segments up to this take the lighter adjoint kernel
 
 struct GaussParams {
   float sigma, inv2s2, inv_s2, cutoff, R;  // R = 3 sigma, cutoff = exp(-R^2/2s^2)

@@ -197,30 +197,44 @@ __global__ __launch_bounds__(kGBlock) void k_splat_emit(MapTable<2> mt, RunArgs 
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Tap weights g(i + 0.5 - x) for the TAPS candidate taps from i0; taps outside
-// [lo, hi) (tile and image bounds) get weight 0.
+constexpr float kLog2E = 1.44269504088896341f;
+
+// Offsets d_a = i0 + a + 0.5 - x of the TAPS candidate taps from i0 (as a - u
+// with u = x - i0 - 0.5, one subtraction per tap), and exp(-d_a^2 / 2 s^2)
+// as exp2(d_a^2 k) with k = -log2(e) / 2 s^2.
 template <int TAPS>
-__device__ __forceinline__ void tap_weights(float x, int i0, int lo, int hi, const GaussParams &gp,
-                                            float g[TAPS]) {
+__device__ __forceinline__ void tap_gauss(float x, int i0, const GaussParams &gp, float d[TAPS],
+                                          float e[TAPS]) {
+  const float u = x - (static_cast<float>(i0) + 0.5f);
+  const float k = -gp.inv2s2 * kLog2E;
 #pragma unroll
   for (int a = 0; a < TAPS; ++a) {
-    const int i = i0 + a;
-    const float d = static_cast<float>(i) + 0.5f - x;
-    const float e = __expf(-d * d * gp.inv2s2) - gp.cutoff;
-    g[a] = (i >= lo && i < hi && fabsf(d) < gp.R) ? e : 0.0f;
+    d[a] = static_cast<float>(a) - u;
+    e[a] = __builtin_amdgcn_exp2f(d[a] * d[a] * k);
   }
+}
+
+// Tap weights g(i + 0.5 - x) for the TAPS candidate taps from i0; taps at
+// distance R or more get weight 0.  Candidates off the image keep their
+// weight: the callers drop them (LDS cells that are never flushed, or a zero
+// upstream gradient).
+template <int TAPS>
+__device__ __forceinline__ void tap_weights(float x, int i0, const GaussParams &gp, float g[TAPS]) {
+  float d[TAPS], e[TAPS];
+  tap_gauss<TAPS>(x, i0, gp, d, e);
+#pragma unroll
+  for (int a = 0; a < TAPS; ++a) g[a] = fabsf(d[a]) < gp.R ? e[a] - gp.cutoff : 0.0f;
 }
 
 // The part of its tile that workgroup b of a per-tile launch takes.  Each
 // tile has p_max consecutive workgroups (consecutive blocks go to different
 // XCDs, so the parts of a dense tile spread over the chip); the tile uses
 // ceil(total / per_part) of them, at most p_max, each with an equal share of
-// the chunks, and walks its runs with groups of 2^log2g lanes
-// where 2^log2g is the first power of two at least the tile's mean run.
-// Returns false (the same in every lane) for a workgroup the tile does not
-// use.  `sums` holds the transpose's column sums of 64-chunk blocks.
+// the chunks.  Returns false (the same in every lane) for a workgroup the
+// tile does not use.  `sums` holds the transpose's column sums of 64-chunk
+// blocks.
 struct TilePart {
-  uint32_t t, c_lo, c_hi, log2g;
+  uint32_t t, c_lo, c_hi;
 };
 __device__ inline bool gauss_tile_part(const uint32_t *__restrict__ sums, uint32_t n_rb,
                                        uint32_t n_chunks, uint32_t p_max, uint32_t per_part,
@@ -239,30 +253,112 @@ __device__ inline bool gauss_tile_part(const uint32_t *__restrict__ sums, uint32
   for (int w = 0; w < kGAccBlock / 64; ++w) total += red[w];
   const uint32_t parts = min(p_max, (total + per_part - 1) / per_part);
   if (part >= parts) return false;
-  const uint32_t mean = total / n_chunks;
-  uint32_t lg = 0;
-  while (lg < 6 && (1u << lg) < mean) ++lg;
   tp->t = t;
   tp->c_lo = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * part / parts);
   tp->c_hi = static_cast<uint32_t>(static_cast<uint64_t>(n_chunks) * (part + 1) / parts);
-  tp->log2g = lg;
   return true;
+}
+
+// The records of a workgroup's tile and chunk range: at most 2^32 - 1 (a
+// tile's records in one launch never reach 2^32).
+__device__ inline uint32_t gauss_part_records(const uint32_t *row0, const uint32_t *row1,
+                                              const TilePart &tp) {
+  __shared__ uint32_t red[kGAccBlock / 64];
+  uint32_t n = 0;
+  for (uint32_t c = tp.c_lo + threadIdx.x; c < tp.c_hi; c += kGAccBlock) n += row1[c] - row0[c];
+  for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = n;
+  __syncthreads();
+  uint32_t total = 0;
+#pragma unroll
+  for (int w = 0; w < kGAccBlock / 64; ++w) total += red[w];
+  return total;
+}
+
+// Calls f(i, rec[i]) once for every record i of a workgroup's tile and chunk
+// range.  The runs are taken kGAccBlock at a time: their lengths are scanned
+// into LDS and the batch's records dealt out evenly, lane j taking records
+// j, j + kGAccBlock, ... of the batch (each found by a binary search over the
+// runs' prefix sums), so no lane idles on short or uneven runs.  A lane loads
+// its next record before it handles the current one.
+template <typename F>
+__device__ __forceinline__ void gauss_part_walk(const float2 *__restrict__ rec, const uint32_t *row0,
+                                                const uint32_t *row1, const TilePart &tp, F &&f) {
+  __shared__ uint32_t run_s[kGAccBlock];  // first record of each run of the batch
+  __shared__ uint32_t run_p[kGAccBlock];  // records of the batch before each run
+  __shared__ uint32_t wtot[kGAccBlock / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  for (uint32_t c0 = tp.c_lo; c0 < tp.c_hi; c0 += kGAccBlock) {
+    const uint32_t c = c0 + tid;
+    const uint32_t s = c < tp.c_hi ? row0[c] : 0u;
+    const uint32_t len = c < tp.c_hi ? row1[c] - s : 0u;
+    uint32_t incl = len;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d, 64);
+      if (lane >= static_cast<uint32_t>(d)) incl += y;
+    }
+    if (lane == 63u) wtot[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (uint32_t v = 0; v < kGAccBlock / 64; ++v) {
+      const uint32_t x = wtot[v];
+      before += v < w ? x : 0u;
+      total += x;
+    }
+    run_s[tid] = s;
+    run_p[tid] = before + incl - len;
+    __syncthreads();
+    // record k of the batch: run r is the last with run_p[r] <= k (k < total,
+    // so r has records and k - run_p[r] is less than its length)
+    auto locate = [&](uint32_t k) {
+      uint32_t r = 0;
+#pragma unroll
+      for (uint32_t step = kGAccBlock / 2; step >= 1; step >>= 1)
+        if (run_p[r + step] <= k) r += step;
+      return run_s[r] + (k - run_p[r]);
+    };
+    uint32_t k = tid, i = 0;
+    float2 r = make_float2(0.0f, 0.0f);
+    if (k < total) {
+      i = locate(k);
+      r = rec[i];
+    }
+    while (k < total) {
+      const uint32_t k2 = k + kGAccBlock;
+      uint32_t i2 = 0;
+      float2 r2 = make_float2(0.0f, 0.0f);
+      if (k2 < total) {
+        i2 = locate(k2);
+        r2 = rec[i2];
+      }
+      f(i, r);
+      k = k2;
+      i = i2;
+      r = r2;
+    }
+    __syncthreads();  // the batch's tables are read up to here
+  }
 }
 
 // One workgroup per (tile, chunk range): the records of its own tile only
 // (binned by their first tap, so every footprint starts at most TAPS - 1
 // pixels left of or above the tile, off the image there, and ends at most
 // TAPS - 1 pixels past its right and lower edges) are read once and their
-// taps summed into an LDS tile with those margins.  The LDS sums are
-// integers: each tap adds round(g(dx) g(dy) 2^31) to a 64-bit counter (LDS
-// integer atomics run far faster than floating-point ones, and integer sums
-// do not depend on their order), so a pixel holds its tap sum to 2^-31 per
-// tap.  Every tap adds, also those of weight 0, so the loop has no branches
-// and its LDS addresses are one base plus constant offsets.  The tile plus
-// its right and lower halo is then scaled by 2^-31 / (N (T - B)) and added
-// into the density with device float atomics (neighbouring tiles and the
-// other chunk ranges of the tile add into the same pixels).  Runs are walked
-// by groups of 2^log2g lanes, one record per lane.
+// taps summed into an LDS tile with those margins.  The LDS sums are 32-bit
+// integers: each tap adds round(g(dx) g(dy) 2^s) with s = clz(C) for the C
+// records of the workgroup, so that C taps of weight at most 1 (each record
+// adds at most one tap to a pixel) stay below 2^32: C < 2^(32 - s).  32-bit
+// LDS integer atomics run at about twice the rate of 64-bit ones and far
+// faster than floating-point ones, and integer sums do not depend on their
+// order; a tap is held to 2^-(s+1), and s >= 21 for parts of up to 2047
+// records (the usual size).
+// Every tap adds, also those of weight 0, so the loop has no branches and
+// its LDS addresses are one base plus constant offsets.  The tile plus its
+// right and lower halo is then scaled by 2^-s / (N (T - B)) and added into
+// the density with device float atomics (neighbouring tiles and the other
+// chunk ranges of the tile add into the same pixels).
 template <int TAPS>
 __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *__restrict__ rec,
                                                                  const uint32_t *__restrict__ tile_start,
@@ -274,44 +370,43 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
   constexpr int H = kGTile + TAPS - 1;  // tile plus right and lower halo, per axis
   constexpr int M = TAPS - 1;           // margin left of and above the tile
   constexpr int HM = H + M;
-  __shared__ unsigned long long acc[HM * HM];
+  __shared__ uint32_t acc[HM * HM];
   TilePart tp;
   if (!gauss_tile_part(sums, n_rb, n_chunks, p_max, per_part, &tp)) return;
   const uint32_t tid = threadIdx.x;
   const int tx = tp.t % gp.tiles_x, ty = tp.t / gp.tiles_x;
   const int x0 = tx * kGTile, y0 = ty * kGTile;
-  const int xhi = min(x0 + H, gp.width), yhi = min(y0 + H, gp.height);
-  for (uint32_t i = tid; i < HM * HM; i += kGAccBlock) acc[i] = 0ull;
-  __syncthreads();
+  for (uint32_t i = tid; i < HM * HM; i += kGAccBlock) acc[i] = 0u;
   const uint32_t *row0 = tile_start + static_cast<size_t>(tp.t) * n_chunks;
   const uint32_t *row1 = row0 + n_chunks;
-  const uint32_t g = 1u << tp.log2g, lane = tid & (g - 1u), groups = kGAccBlock >> tp.log2g;
-  for (uint32_t c = tp.c_lo + (tid >> tp.log2g); c < tp.c_hi; c += groups) {
-    const uint32_t s = row0[c], e = row1[c];
-    for (uint32_t i = s + lane; i < e; i += g) {
-      const float2 r = rec[i];
-      const int i0 = first_tap(r.x, gp.R), j0 = first_tap(r.y, gp.R);
-      // taps left of or above the tile are off the image (first taps are
-      // clamped to 0 for binning), so lo = x0, y0 drops exactly those
-      float gx[TAPS], gy[TAPS];
-      tap_weights<TAPS>(r.x, i0, x0, xhi, gp, gx);
-      tap_weights<TAPS>(r.y, j0, y0, yhi, gp, gy);
-      unsigned long long *base = acc + (j0 - y0 + M) * HM + (i0 - x0 + M);
+  const uint32_t n_rec = gauss_part_records(row0, row1, tp);  // synchronises the clear too
+  const int sh = n_rec ? __clz(n_rec) : 31;
+  const float scale = __uint_as_float(static_cast<uint32_t>(127 + sh) << 23);  // 2^sh
+  gauss_part_walk(rec, row0, row1, tp, [&](uint32_t, float2 r) {
+    const int i0 = first_tap(r.x, gp.R), j0 = first_tap(r.y, gp.R);
+    // taps left of or above the tile are off the image (first taps are
+    // clamped to 0 for binning) and land in the margins; taps past the
+    // image's right or lower edge land in halo cells outside the image:
+    // neither is flushed
+    float gx[TAPS], gy[TAPS];
+    tap_weights<TAPS>(r.x, i0, gp, gx);
+    tap_weights<TAPS>(r.y, j0, gp, gy);
+    uint32_t *base = acc + (j0 - y0 + M) * HM + (i0 - x0 + M);
 #pragma unroll
-      for (int b = 0; b < TAPS; ++b) {
-        const float wy = gy[b] * 2147483648.0f;  // 2^31; g <= 1 per axis
+    for (int b = 0; b < TAPS; ++b) {
+      const float wy = gy[b] * scale;  // g <= 1 per axis
+      // round to nearest: truncate the product plus 1/2 (gx wy < 2^s, so
+      // the tap is at most 2^s)
 #pragma unroll
-        for (int a = 0; a < TAPS; ++a)
-          atomicAdd(base + b * HM + a, static_cast<unsigned long long>(__float2uint_rn(gx[a] * wy)));
-      }
+      for (int a = 0; a < TAPS; ++a)
+        atomicAdd(base + b * HM + a, static_cast<uint32_t>(fmaf(gx[a], wy, 0.5f)));
     }
-  }
-  __syncthreads();
-  const double unit = static_cast<double>(gp.weight) * 0x1p-31;
+  });
+  const double unit = ldexp(static_cast<double>(gp.weight), -sh);
   for (uint32_t i = tid; i < H * H; i += kGAccBlock) {
     const int px = x0 + static_cast<int>(i % H), py = y0 + static_cast<int>(i / H);
-    const unsigned long long v = acc[(i / H + M) * HM + i % H + M];
-    if (px < gp.width && py < gp.height && v != 0ull)
+    const uint32_t v = acc[(i / H + M) * HM + i % H + M];
+    if (px < gp.width && py < gp.height && v != 0u)
       atomicAdd(dens + static_cast<size_t>(py) * gp.width + px,
                 static_cast<float>(static_cast<double>(v) * unit));
   }
@@ -323,27 +418,27 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_accumulate(const float2 *_
 // dL/dx, dL/dy (in pixels, before the chain to positions) of one splat at
 // pixel coordinates (x, y): the taps' weights g and derivatives dg against
 // the upstream gradient G, read through `at(row, col)` for every candidate
-// tap (those without a weight or a derivative add exact zeros, so the sums
-// are those over the taps that have one; `at` must accept every candidate).
+// tap.  `at` must accept every candidate and return 0 for those off the
+// image, and taps at distance R or more get g = dg = 0, so every tap without
+// a weight adds an exact zero and the sums are those over the image's taps.
 template <int TAPS, typename GAt>
 __device__ __forceinline__ void splat_grad_px(float x, float y, const GaussParams &gp, GAt at,
                                               float *ax_out, float *ay_out) {
   const int i0 = first_tap(x, gp.R), j0 = first_tap(y, gp.R);
   float gx[TAPS], dgx[TAPS], gy[TAPS], dgy[TAPS];
+  {
+    float dx[TAPS], ex[TAPS], dy[TAPS], ey[TAPS];
+    tap_gauss<TAPS>(x, i0, gp, dx, ex);
+    tap_gauss<TAPS>(y, j0, gp, dy, ey);
 #pragma unroll
-  for (int a = 0; a < TAPS; ++a) {
-    const int i = i0 + a;
-    const float d = static_cast<float>(i) + 0.5f - x;
-    const float e = __expf(-d * d * gp.inv2s2);
-    const bool on = i >= 0 && i < gp.width && fabsf(d) < gp.R;
-    gx[a] = on ? e - gp.cutoff : 0.0f;
-    dgx[a] = on ? -d * gp.inv_s2 * e : 0.0f;
-    const int jj = j0 + a;
-    const float dy = static_cast<float>(jj) + 0.5f - y;
-    const float ey = __expf(-dy * dy * gp.inv2s2);
-    const bool ony = jj >= 0 && jj < gp.height && fabsf(dy) < gp.R;
-    gy[a] = ony ? ey - gp.cutoff : 0.0f;
-    dgy[a] = ony ? -dy * gp.inv_s2 * ey : 0.0f;
+    for (int a = 0; a < TAPS; ++a) {
+      const bool on = fabsf(dx[a]) < gp.R;
+      gx[a] = on ? ex[a] - gp.cutoff : 0.0f;
+      dgx[a] = on ? -dx[a] * gp.inv_s2 * ex[a] : 0.0f;
+      const bool ony = fabsf(dy[a]) < gp.R;
+      gy[a] = ony ? ey[a] - gp.cutoff : 0.0f;
+      dgy[a] = ony ? -dy[a] * gp.inv_s2 * ey[a] : 0.0f;
+    }
   }
   float ax = 0.0f, ay = 0.0f;
 #pragma unroll
@@ -394,27 +489,27 @@ __global__ __launch_bounds__(kGAccBlock) void k_splat_grad_tiles(
   __syncthreads();
   // every candidate tap lies in [x0 - M, x0 + H) x [y0 - M, y0 + H) (records
   // are binned by their first tap; taps left of or above the tile are off the
-  // image and read the zero margin)
+  // image and read the zero margin, taps past its right or lower edge read
+  // the zeros loaded there)
   auto at = [&](int row, int col) { return g[(row - y0 + M) * HM + (col - x0 + M)]; };
   const float cx = -gp.scale[0] * gp.weight, cy = -gp.scale[1] * gp.weight;
   const uint32_t *row0 = tile_start + static_cast<size_t>(tp.t) * n_chunks;
   const uint32_t *row1 = row0 + n_chunks;
-  const uint32_t gsz = 1u << tp.log2g, lane = tid & (gsz - 1u), groups = kGAccBlock >> tp.log2g;
-  for (uint32_t c = tp.c_lo + (tid >> tp.log2g); c < tp.c_hi; c += groups) {
-    const uint32_t s = row0[c], e = row1[c];
-    for (uint32_t i = s + lane; i < e; i += gsz) {
-      const float2 r = rec[i];
-      float ax, ay;
-      splat_grad_px<TAPS>(r.x, r.y, gp, at, &ax, &ay);
-      S[i] = make_float2(ax * cx, ay * cy);
-    }
-  }
+  gauss_part_walk(rec, row0, row1, tp, [&](uint32_t i, float2 r) {
+    float ax, ay;
+    splat_grad_px<TAPS>(r.x, r.y, gp, at, &ax, &ay);
+    S[i] = make_float2(ax * cx, ay * cy);
+  });
 }
 
 // The adjoint sweep of each point of a launch slice, with the splat
 // gradients already computed per tile: splat t of point n has its gradient
 // at S[pos[t - B - 1][n]] (none if pos holds kGInvalid: off the image).
-template <int NG, bool EQUAL>
+// SEG bounds the checkpoint interval: a segment's positions and map indices
+// stay in registers (3 (SEG + 1) of them), so the common intervals up to 8
+// take a kernel with half the live registers (twice the resident waves to
+// hide the gathers of S) of the one for intervals up to 16.
+template <int NG, bool EQUAL, int SEG>
 __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, RunArgs ra,
                                                                const uint32_t *__restrict__ pos,
                                                                const float2 *__restrict__ S,
@@ -444,17 +539,28 @@ __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, R
     for (int seg = static_cast<int>(n_seg) - 1; seg >= 0; --seg) {
       const uint32_t t_start = static_cast<uint32_t>(seg) * c;
       const uint32_t len = min(c, T - t_start);
-      float px[kMaxSeg + 1], py[kMaxSeg + 1];
-      int ks[kMaxSeg + 1];
+      float px[SEG + 1], py[SEG + 1];
+      int ks[SEG + 1];
       const float2 p0 = reinterpret_cast<const float2 *>(ck.ckpt)[static_cast<size_t>(seg) * ck.stride + n];
       px[0] = p0.x;
       py[0] = p0.y;
       ks[0] = 0;
+      // the segment's splat gradients, gathered first so that their latency
+      // hides under the recompute (the gathers do not depend on it)
+      float2 sv[SEG + 1];
+#pragma unroll
+      for (int m = 1; m <= SEG; ++m) {
+        const uint32_t t = t_start + m;
+        uint32_t q = kGInvalid;
+        if (static_cast<uint32_t>(m) <= len && t > B)
+          q = pos[static_cast<size_t>(t - B - 1) * ra.n_points + n];
+        sv[m] = q != kGInvalid ? S[q] : make_float2(0.0f, 0.0f);
+      }
       // recompute the segment exactly as the forward pass did
       Block4 blk{0u, 0u, 0u, 0u};
       float p[2] = {p0.x, p0.y};
 #pragma unroll
-      for (int m = 1; m <= kMaxSeg; ++m) {
+      for (int m = 1; m <= SEG; ++m) {
         if (static_cast<uint32_t>(m) > len) break;
         const uint32_t t = t_start + m;
         if (m == 1 || ((t - 1) & 3u) == 0u)
@@ -472,18 +578,9 @@ __global__ __launch_bounds__(kGBwdBlock) void k_splat_backward(MapTable<2> mt, R
       }
       // reverse sweep
 #pragma unroll
-      for (int m = kMaxSeg; m >= 1; --m) {
+      for (int m = SEG; m >= 1; --m) {
         if (static_cast<uint32_t>(m) > len) continue;
-        const uint32_t t = t_start + m;
-        float s0 = 0.0f, s1 = 0.0f;
-        if (t > B) {
-          const uint32_t q = pos[static_cast<size_t>(t - B - 1) * ra.n_points + n];
-          if (q != kGInvalid) {
-            const float2 sv = S[q];
-            s0 = sv.x;
-            s1 = sv.y;
-          }
-        }
+        const float s0 = sv[m].x, s1 = sv[m].y;
         float c0 = 0.0f, c1 = 0.0f;
         if (k_next >= 0) {
           const float *A = table + k_next * 8;  // a00 a01 a10 a11: A^T lam
@@ -620,15 +717,23 @@ hipError_t launch_splat_forward(const GaussJob &j, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int NG>
+template <int NG, int SEG>
 static void launch_sweep(const GaussJob &j, uint32_t block_offset, hipStream_t s) {
   const uint32_t blocks = (j.ra.n_points + kGBwdBlock - 1) / kGBwdBlock;
   if (j.equal)
-    hipLaunchKernelGGL((k_splat_backward<NG, true>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt, j.ra,
-                       j.gb.pos, j.S, j.ck, j.partials, block_offset);
+    hipLaunchKernelGGL((k_splat_backward<NG, true, SEG>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt,
+                       j.ra, j.gb.pos, j.S, j.ck, j.partials, block_offset);
   else
-    hipLaunchKernelGGL((k_splat_backward<NG, false>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt, j.ra,
-                       j.gb.pos, j.S, j.ck, j.partials, block_offset);
+    hipLaunchKernelGGL((k_splat_backward<NG, false, SEG>), dim3(blocks), dim3(kGBwdBlock), 0, s, j.mt,
+                       j.ra, j.gb.pos, j.S, j.ck, j.partials, block_offset);
+}
+
+template <int NG>
+static void launch_sweep(const GaussJob &j, uint32_t block_offset, hipStream_t s) {
+  if (j.ck.every <= kShortSeg)
+    launch_sweep<NG, kShortSeg>(j, block_offset, s);
+  else
+    launch_sweep<NG, kMaxSeg>(j, block_offset, s);
 }
 
 hipError_t launch_splat_backward_slice(const GaussJob &j, uint32_t block_offset, hipStream_t s) {
