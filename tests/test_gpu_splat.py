@@ -230,6 +230,24 @@ def test_concentrated_tile_parts(api, orc):
     assert np.linalg.norm(g.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-4
 
 
+def test_long_runs_many_chunk_batches(api, orc):
+    # 400 iterations of 2^14 points: 33 flushes of 32 blocks, 1056 chunks, so
+    # a sparse tile's one or two workgroups walk its runs in several batches
+    # of 256 (some runs empty), and dense tiles' workgroups in one
+    w = W.differentiable(n_points=1 << 14, n_iters=400, burn_in=8)
+    img, ckpt = gpu_forward(api, w["system"], w["run"], w["image"], 1.0, 8)
+    got = img.data.cpu().numpy().astype(np.float64)
+    ref = orc.splat_gauss(w["system"], w["run"], w["image"], 1.0)
+    assert np.max(np.abs(got - ref)) / np.max(ref) < 2e-5
+    assert abs(got.sum() - ref.sum()) / ref.sum() < 1e-5
+    G = _upstream(orc, w).astype(np.float32)
+    g = api.splat_backward(w["system"], w["run"], img, 1.0, torch.from_numpy(G).to(_dev()),
+                           ckpt, 8).cpu().numpy().astype(np.float64)
+    ref_g = orc.splat_gauss_backward(w["system"], w["run"], w["image"], 1.0,
+                                     G.astype(np.float64))
+    assert np.linalg.norm(g - ref_g) / np.linalg.norm(ref_g) < 1e-4
+
+
 def test_density_many_tiles(api, orc):
     # 1440 x 1440 pixels: 2025 tiles of 32 x 32, fewer workgroups per tile
     w = W.differentiable(n_points=1 << 15, n_iters=16, burn_in=4)
