@@ -138,7 +138,8 @@ STEP_KERNELS = {
                ("k_depth_accumulate", "tile_accumulate"), ("k_fill", "image_clear")),
     "cfs_square": (("k_chaos_binned", "chaos_kernel"), ("k_transpose", "table_transpose"),
                    ("k_tile_accumulate", "tile_accumulate"), ("k_fill", "image_clear")),
-    "sierpinski": (("k_chaos", "chaos_kernel"), ("k_fill", "image_clear")),
+    "sierpinski": (("k_chaos_binned", "chaos_kernel"), ("k_transpose", "table_transpose"),
+                   ("k_tile_accumulate", "tile_accumulate"), ("k_fill", "image_clear")),
     "circle": (("k_chaos_binned", "chaos_kernel"), ("k_transpose", "table_transpose"),
                ("k_tile_accumulate", "tile_accumulate"), ("k_fill", "image_clear")),
     "circle_mixed": (("k_chaos_binned", "chaos_kernel"), ("k_transpose", "table_transpose"),
@@ -204,6 +205,8 @@ def summarise_trace(directory, log_path, workload, precision, steps=5, warmup=2,
     mine = [r for r in trace if frag + "<" in r["Kernel_Name"]]
     mine.sort(key=lambda r: int(r["Start_Timestamp"]))
     per_step = len(mine) // (steps + warmup)
+    if per_step == 0:
+        raise SystemExit(f"no {frag} launches in {directory}")
     timed = mine[warmup * per_step:]
     dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6 for r in timed]
     step_ms = float(np.sum(dur)) / steps
