@@ -712,7 +712,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10,
+                    help="untimed steps first (the chaos kernel still speeds up over the "
+                         "first several launches of a process)")
     ap.add_argument("--workload", choices=["menger", "cfs_square", "sierpinski", "circle",
                                            "circle_mixed"],
                     default="menger", help="the headline configuration")
