@@ -7,18 +7,20 @@
 // density is a continuous function of the map parameters).  Like the integer
 // splat, the taps are not applied with device atomics: each splat becomes one
 // (x, y) record, records are sorted in LDS by the 32x32-pixel tile that holds
-// their footprint's first tap, and a per-tile kernel evaluates the taps of the
-// records of its own tile and of its left, upper and upper-left neighbours
-// (a footprint of at most 16 taps spans at most two tiles per axis) into an
-// LDS tile.  Checkpoints of the positions every c iterations are written for
-// the backward pass.
+// their footprint's first tap, and per-tile workgroups sum the taps of their
+// tile's records as integers into an LDS tile with a margin of TAPS - 1
+// pixels on every side (a footprint of at most 16 taps reaches at most that
+// far past its tile), then add it to the density.  Checkpoints of the
+// positions every c iterations are written for the backward pass.
 //
-// Backward: per point, each checkpoint segment is recomputed into registers
-// and swept in reverse with the adjoint
+// Backward: the records are emitted again, each with its index per (step,
+// point); per-tile workgroups compute every splat's gradient s_t from an LDS
+// copy of dL/dD; then per point each checkpoint segment is recomputed into
+// registers and swept in reverse with the adjoint
 //   lam_t = s_t + A_{k_{t+1}}^T lam_{t+1},  dA_{k_t} += lam_t p_{t-1}^T,
-//   db_{k_t} += lam_t,
-// where s_t gathers dL/dD over the splat's taps.  Gradients stay in registers
-// per lane and are reduced in a fixed order (no floating-point atomics).
+//   db_{k_t} += lam_t.
+// Gradients stay in registers per lane and are reduced in a fixed order (no
+// floating-point atomics).
 #include "cfs_device.hpp"
 #include "cfs_host.hpp"
 

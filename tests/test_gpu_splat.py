@@ -231,9 +231,9 @@ def test_concentrated_tile_parts(api, orc):
 
 
 def test_long_runs_many_chunk_batches(api, orc):
-    # 400 iterations of 2^14 points: 33 flushes of 32 blocks, 1056 chunks, so
-    # a sparse tile's one or two workgroups walk its runs in several batches
-    # of 256 (some runs empty), and dense tiles' workgroups in one
+    # 400 iterations of 2^14 points: dozens of flushes of 32 blocks, over a
+    # thousand chunks, so a sparse tile's one or two workgroups walk its runs
+    # in several batches of 256 (some runs empty), dense tiles' in one
     w = W.differentiable(n_points=1 << 14, n_iters=400, burn_in=8)
     img, ckpt = gpu_forward(api, w["system"], w["run"], w["image"], 1.0, 8)
     got = img.data.cpu().numpy().astype(np.float64)
