@@ -60,7 +60,9 @@ def test_density_parity(api, orc, sigma):
 SIGMAS = [1.0, 1.01, 2.0, 2.5]
 
 
-@pytest.mark.parametrize("sigma", SIGMAS)
+# below 1 px most of the 6 candidate taps per axis lie at distance R = 3
+# sigma or more and take weight 0 (at 0.3 px one or two taps per axis remain)
+@pytest.mark.parametrize("sigma", [0.3, 0.6] + SIGMAS)
 def test_density_ragged_and_offimage(api, orc, sigma):
     # ragged image (not a multiple of the 32-pixel tile), window cutting the
     # attractor so that footprints straddle and leave the image; the
