@@ -150,3 +150,32 @@ def test_summarise_trace_fraction(tmp_path):
     # 4 timed launches of 1.5 ms per step: 6.0 ms; 1.2e11 / 6 ms / 40 T = 0.5
     assert "6.000 ms per step in the trace" in text
     assert "**0.500**" in text
+
+
+def test_summarise_trace_refuses_a_trace_without_the_kernel(tmp_path):
+    """A trace whose kernels do not include the workload's roofline kernel
+    (here the Sierpinski configuration's binned chaos kernel) is refused,
+    not summarised as a zero-length step."""
+    import pytest
+    import bench
+    assert bench.STEP_KERNELS["sierpinski"][0][0] == "k_chaos_binned"
+    other = "void cfs::k_chaos<float, 2, 0, true, false, false>(args)"
+    header = ["Kind", "Agent_Id", "Queue_Id", "Stream_Id", "Thread_Id", "Dispatch_Id",
+              "Kernel_Id", "Kernel_Name", "Correlation_Id", "Start_Timestamp", "End_Timestamp",
+              "LDS_Block_Size", "Scratch_Size", "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count",
+              "Workgroup_Size_X", "Workgroup_Size_Y", "Workgroup_Size_Z", "Grid_Size_X",
+              "Grid_Size_Y", "Grid_Size_Z"]
+    rows = [["KERNEL_DISPATCH", "Agent 1", 1, 0, 1, i + 1, 7, other, i + 1, 1000 * i,
+             1000 * i + 500, 0, 0, 32, 0, 32, 512, 1, 1, 1 << 16, 1, 1] for i in range(7)]
+    _write_csv(str(tmp_path / "t" / "s_kernel_trace.csv"), header, rows)
+    _write_csv(str(tmp_path / "t" / "s_kernel_stats.csv"),
+               ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs",
+                "StdDev"], [[other, 7, 3500.0, 500.0, 100.0, 500.0, 500.0, 0.0]])
+    line = {"metric": "m", "ms_per_step": 0.07, "config": {"workload": "sierpinski: test"},
+            "phase_ms": {"chaos_kernel": 0.03}, "roofline": {"lane_ops_per_step": 1.8e8,
+                                                             "peak": 39.3, "frac": 0.13}}
+    log = tmp_path / "run.log"
+    log.write_text(json.dumps(line) + "\n")
+    with pytest.raises(SystemExit, match="no k_chaos_binned launches"):
+        bench.summarise_trace(str(tmp_path / "t"), str(log), "sierpinski", "f32",
+                              out_dir=str(tmp_path))
