@@ -138,6 +138,30 @@ def test_no_splats_gradient_zero(api):
     assert torch.count_nonzero(grad).item() == 0
 
 
+def test_no_points_and_every_splat_off_the_image(api, orc):
+    # no points: nothing is read or written, the gradient is exactly zero;
+    # a window that misses the attractor: every splat is dropped (and
+    # counted), the density stays zero and so does the gradient
+    w = W.differentiable(n_points=4096, n_iters=12, burn_in=2, side=64)
+    empty = dict(w["run"], n_points=0)
+    img = api.Image(w["image"], device=_dev()).clear()
+    ckpt = torch.empty((api.n_checkpoints(12, 4), 1, 2), dtype=torch.float32, device=_dev())
+    api.splat(w["system"], empty, img, 1.0, ckpt=ckpt, ckpt_every=4)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(img.data).item() == 0 and img.dropped.item() == 0
+    G = torch.randn((64, 64), dtype=torch.float32, device=_dev())
+    g = api.splat_backward(w["system"], empty, img, 1.0, G, ckpt, 4)
+    assert torch.count_nonzero(g).item() == 0
+    far = dict(w["image"], lo=[5.0, 5.0], hi=[6.0, 6.0])
+    img2, ck2 = gpu_forward(api, w["system"], w["run"], far, 1.0, 4)
+    assert torch.count_nonzero(img2.data).item() == 0
+    ref = orc.splat_gauss(w["system"], w["run"], far, 1.0)
+    assert np.count_nonzero(ref) == 0
+    assert img2.dropped.item() == 4096 * 10
+    g2 = api.splat_backward(w["system"], w["run"], img2, 1.0, G, ck2, 4)
+    assert torch.count_nonzero(g2).item() == 0
+
+
 def test_gradient_vs_finite_differences(api, orc):
     # parameters with 12 fractional bits so that +-h (a power of two) is exact
     w = W.differentiable(n_points=2048, n_iters=16, burn_in=4, side=64)
