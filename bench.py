@@ -108,15 +108,23 @@ def measured_valu(workload, precision):
 
 
 def _pmc_rows(directory, counter):
-    """(kernel name, value) of every dispatch in a rocprofv3 --pmc CSV run."""
+    """(kernel name, value) of every dispatch in a rocprofv3 --pmc CSV run.
+    A folder that holds the files of several runs (one per process id, when
+    output folders are reused) is read for its newest run only."""
     import csv
     import glob
+    paths = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not paths:
+        raise SystemExit(f"no counter files under {directory}")
+    newest = max(paths, key=os.path.getmtime)
+    if len(paths) > 1:
+        print(f"{directory}: {len(paths)} runs, reading the newest ({os.path.basename(newest)})",
+              file=sys.stderr)
     rows = []
-    for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
-        with open(path, newline="") as fh:
-            for r in csv.DictReader(fh):
-                if r.get("Counter_Name") == counter:
-                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    with open(newest, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
     if not rows:
         raise SystemExit(f"no {counter} rows under {directory}")
     return rows

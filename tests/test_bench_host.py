@@ -179,3 +179,28 @@ def test_summarise_trace_refuses_a_trace_without_the_kernel(tmp_path):
     with pytest.raises(SystemExit, match="no k_chaos_binned launches"):
         bench.summarise_trace(str(tmp_path / "t"), str(log), "sierpinski", "f32",
                               out_dir=str(tmp_path))
+
+
+def test_summarise_pmc_reads_the_newest_run_only(tmp_path):
+    """An output folder reused by two profiled runs holds two counter files;
+    only the newer run's dispatches count (an older run would double the
+    bytes per step)."""
+    import time
+    import bench
+    chaos = "void cfs::k_chaos_depth_binned<double, true, 2>(args)"
+    copy = "__amd_rocclr_copyBuffer"
+    for sub, v in (("f", 10.0), ("w", 2000.0)):
+        counter = "FETCH_SIZE" if sub == "f" else "WRITE_SIZE"
+        old = [(copy, 262144.0)] + [(chaos, 999.0 * v)] * 3
+        new = [(copy, 262144.0)] + [(chaos, v)] * 3
+        _write_csv(str(tmp_path / sub / "vm" / "1_counter_collection.csv"), _COUNTER_HEADER,
+                   _counter_rows(counter, old))
+        time.sleep(0.05)
+        _write_csv(str(tmp_path / sub / "vm" / "2_counter_collection.csv"), _COUNTER_HEADER,
+                   _counter_rows(counter, new))
+        os.utime(str(tmp_path / sub / "vm" / "1_counter_collection.csv"), (1.0e9, 1.0e9))
+    bench.summarise_pmc(str(tmp_path / "f"), str(tmp_path / "w"), "menger", "f64",
+                        out_dir=str(tmp_path))
+    k = json.load(open(tmp_path / "traffic_menger_f64.json"))["kernels"]
+    assert k["chaos_kernel"]["FETCH_SIZE"] == 3 * 10.0 / 3 * 1024
+    assert k["chaos_kernel"]["WRITE_SIZE"] == 3 * 2000.0 / 3 * 1024
